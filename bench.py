@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the COLA particle-mesh run on one MI355X.
+
+A bench step is one pass of the whole hot path on one batch of synthetic input:
+2LPT initial conditions from white noise, the COLA steps (CIC deposit, r2c FFT,
+Poisson + gradient, three c2r FFTs, CIC gather + kick + drift) and the closing
+kick with L+.  Inputs (the white noise) are resident in HBM before timing starts.
+
+value = np^3 * n_steps / (seconds per bench step): whole-job particle-steps/s.
+Also reported: the per-COLA-step time (cola_step, median over steps), each
+kernel stage's time from HIP events on the launch stream, the roofline of the
+dominant kernel (algorithmic bytes per launch / its mean duration against the
+8 TB/s HBM peak) and the FP64 CPU oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    # name: (np, nm, box, seed, description)
+    "c0": (32, 64, 100.0, 1301, "32^3 particles / 64^3 mesh, 100 Mpc/h"),
+    "c1": (256, 512, 100.0, 1302, "256^3 particles / 512^3 mesh, 100 Mpc/h"),
+    "c2": (512, 1024, 400.0, 1303, "512^3 particles / 1024^3 mesh, 400 Mpc/h"),
+    "c4": (128, 256, 100.0, 11, "128^3 particles / 256^3 mesh, 100 Mpc/h"),
+}
+
+
+def stage_bytes(np_side: int, nm: int) -> dict:
+    """Algorithmic HBM bytes per launch of each stage (each array read and written
+    once per pass; R = nm^3 reals, C = nm^2 (nm/2 + 1) complex, P = np^3)."""
+    R = nm**3
+    C = nm * nm * (nm // 2 + 1)
+    P = np_side**3
+    Rp = np_side**3
+    Cp = np_side * np_side * (np_side // 2 + 1)
+    return {
+        "deposit": 12 * P + 4 * R,
+        "fft_z_fwd": 4 * R + 8 * C,
+        "fft_y_fwd": 16 * C,
+        "fft_x_poisson": 8 * C + 24 * C,
+        "fft_y_inv": 48 * C,
+        "fft_z_inv": 24 * C + 12 * R,
+        "gather_kick_drift": 12 * R + 72 * P,
+        "gather_finish": 12 * R + 48 * P + 36 * P,
+        "fill": 0,
+        # 2LPT on the particle grid (per launch; the x and y passes handle 9 or 3 fields)
+        "lpt_fft_z_fwd": 4 * Rp + 8 * Cp,
+        "lpt_fft_y_fwd": 16 * Cp,
+        "lpt_fft_x_mul": 8 * Cp + 6 * 8 * Cp,       # mean of the 9- and 3-output launches
+        "lpt_fft_y_inv": 6 * 16 * Cp,
+        "lpt_fft_z_inv": 3 * (8 * Cp + 4 * Rp) + 3 * 4 * Rp,
+        "lpt_hessian": 6 * 8 * Cp + 4 * Rp,
+    }
+
+
+def b_alg_step(np_side: int, nm: int) -> int:
+    R = nm**3
+    C = nm * nm * (nm // 2 + 1)
+    return 84 * np_side**3 + 32 * R + 128 * C
+
+
+def csrc_digest() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1301_0322_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(stage: str, workload: str):
+    """HBM bytes per launch from the committed PMC summary, if it is for this
+    kernel source and workload; None otherwise."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{stage}_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_digest") != csrc_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(np_side: int, nm: int, box: float, seed: int) -> dict:
+    """The FP64 oracle on one COLA step of the same workload (ICs untimed)."""
+    import numpy as np
+    import torch
+    from oracle import cola as ocola
+    from oracle import cosmology as cosmo
+    from oracle import lpt, philox
+
+    cfg = cosmo.Config(np_side=np_side, nm_side=nm, box=box)
+    w = philox.white_noise(seed, np_side**3)
+    table = cosmo.step_table(cfg)
+    s1, s2 = lpt.lpt_from_noise(w, cfg)
+    st = ocola.initial_state(s1, s2, table)
+    t0 = time.perf_counter()
+    st = ocola.step(st, 0, table, cfg)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(st.s.sum().item())
+    return {
+        "value": np_side**3 / dt, "unit": "particle-steps/s", "cores": torch.get_num_threads(),
+        "kind": "oracle",
+        "sample": f"one COLA step (PM force, kick, drift) of the {np_side}^3/{nm}^3 workload in FP64 "
+                  f"torch-CPU, after oracle 2LPT ICs from the same Philox seed (ICs untimed); "
+                  f"{dt:.1f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c1", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU form of this method is described, not built)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_1301_0322_amd as cola
+
+    np_side, nm, box, seed, desc = CONFIGS[args.config]
+    torch.cuda.set_device(0)
+    cfg = cola.Config(np=np_side, nm=nm, box=box)
+    plan = cola.Plan(cfg)
+    ws = plan.workspace()
+    p = cola.Particles.empty(np_side)
+    w = torch.empty(np_side**3, dtype=torch.float32, device="cuda")
+    plan.noise(seed, w)
+    x = torch.empty((3, np_side**3), dtype=torch.float32, device="cuda")
+    v = torch.empty_like(x)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.run(w, p, x, v, ws)
+    torch.cuda.synchronize()
+
+    # timed region: K whole runs, HIP events on the launch stream around every kernel
+    plan.trace_enable(True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        plan.run(w, p, x, v, ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    run_ms = e0.elapsed_time(e1) / args.steps
+    stages = plan.trace_read()
+    plan.trace_enable(False)
+    if not np.isfinite(x.sum().item()):
+        raise RuntimeError("non-finite positions")
+
+    # per-COLA-step time: cola_step alone, median over steps 1..n-1
+    plan.init_2lpt(w, p, ws)
+    step_ms = []
+    for i in range(cfg.n_steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        plan.step(i, p, ws)
+        b.record(stream)
+        b.synchronize()
+        if i > 0:
+            step_ms.append(a.elapsed_time(b))
+    pm_step_ms = float(np.median(step_ms))
+
+    sb = stage_bytes(np_side, nm)
+    per_run = {k: {"ms": ms / args.steps, "launches": n // args.steps, "ms_per_launch": ms / n}
+               for k, (ms, n) in stages.items()}
+    dom = max(stages, key=lambda k: stages[k][0])
+    dom_ms_launch = stages[dom][0] / stages[dom][1]
+    dom_bytes = sb.get(dom, 0)
+    achieved = dom_bytes / (dom_ms_launch * 1e-3) / 1e9
+    workload = f"{args.config}"
+    traffic = read_traffic(dom, workload)
+    b_alg = b_alg_step(np_side, nm)
+
+    out = {
+        "metric": "particle-steps/s, 256^3 COLA PM step",
+        "value": np_side**3 * cfg.n_steps / (run_ms * 1e-3),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": run_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"cola_run: 2LPT ICs + {cfg.n_steps} COLA steps z=9->0 + final kick, {desc}, "
+                               f"Philox white noise seed {seed}, BBKS LCDM",
+                   "np": np_side, "nm": nm, "box_mpc_h": box, "n_steps": cfg.n_steps},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms_launch},
+        "pm_step": {"ms": pm_step_ms, "particle_steps_per_s": np_side**3 / (pm_step_ms * 1e-3),
+                    "b_alg_bytes": b_alg, "hbm_frac": b_alg / (pm_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)},
+        "stages_per_run": per_run,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(np_side, nm, box, seed)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,181 @@
+/*
+ * cola.h -- C ABI of the MI355X (gfx950) COLA particle-mesh library.
+ *
+ * Method: Tassev, Zaldarriaga & Eisenstein, "Solving Large Scale Structure in Ten
+ * Easy Steps with COLA" (arXiv:1301.0322).  The library evolves N = np^3 particles
+ * with the COLA scheme: the time evolution of eq. (ALCtimestep), the frame
+ * transforms of eq. (Lops) and the modified kick / drift operators of eq. (KDKALC),
+ * with the force -(3/2) Om a d_x d_x^-2 delta of eq. (eom) computed by a
+ * particle-mesh method (Section 2), and 2LPT initial conditions (Section 2,
+ * Appendix A.3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Particles: index p = (i*np + j)*np + k (k fastest), Lagrangian position
+ *   q = (i, j, k) * box / np.  Per-particle vectors are SoA float arrays [3][np^3]
+ *   (component d of particle p at d*np^3 + p), in Mpc/h.
+ *   s  = x - q, the displacement (positions are stored as displacements);
+ *   v  = v_res = T[s_res], the residual velocity of Appendix A.3 (scaled canonical
+ *        velocity a^2 dx/dt / H0, in Mpc/h, measured by an LPT observer);
+ *   s1, s2 = Zel'dovich and second-order displacements at a = 1 (D1(1) = 1,
+ *        D2 ~ -3/7 D1^2).
+ * - Mesh: nm^3 cells, C order [x][y][z], z fastest; value c is the cell centred at
+ *   (c + 1/2) * box / nm.  Mass assignment is cloud-in-cell with particle mass
+ *   (nm/np)^3, so the mean density is 1.
+ * - Poisson solve: continuum kernel -1/k^2, spectral gradient i k, k = 0 and every
+ *   mode with a Nyquist index set to zero.
+ * - Every pointer argument named as device memory must be a device allocation of
+ *   the current HIP device (e.g. a torch CUDA/HIP tensor).  Arrays are not checked
+ *   for size: the caller owns them and must pass at least the stated length.
+ * - stream is a hipStream_t (passed as void*; NULL = the default stream).  Every
+ *   call that takes a stream only enqueues work on it: it neither synchronises
+ *   nor allocates device memory, except that the first such call on a plan uploads
+ *   the plan's small tables (twiddles, spectrum table) to the current device.
+ * - ws is the caller-owned device workspace of at least cola_workspace_bytes()
+ *   bytes, 256-byte aligned.  Calls that share a workspace must be ordered on one
+ *   stream.
+ * - Status: 0 on success, a negative COLA_ERR_* code otherwise; no exception or
+ *   abort crosses this ABI.  cola_strerror() describes a code; after COLA_ERR_HIP,
+ *   cola_last_hip_error() returns the hipError_t of the calling thread.
+ */
+#ifndef COLA_H
+#define COLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define COLA_OK 0
+#define COLA_ERR_INVALID (-1)          /* null pointer or inconsistent parameter */
+#define COLA_ERR_UNSUPPORTED_SIZE (-2) /* np or nm not in the supported size list */
+#define COLA_ERR_RANGE (-3)            /* step index out of range */
+#define COLA_ERR_HIP (-4)              /* a HIP runtime call failed */
+#define COLA_ERR_DEVICE (-5)           /* plan used on a different device than its tables */
+
+/* Variant flags (eq. KDKALC is the default). */
+#define COLA_FLAG_KDK_STD 0x1u      /* standard COLA discretisation, eq. (KDKALCstd) */
+#define COLA_FLAG_NO_LPT_FRAME 0x2u /* plain PM leapfrog, eq. (KDKStd): s1 = s2 = 0 in the operators */
+#define COLA_FLAG_LOG_A_STEPS 0x4u  /* timesteps uniform in log a (Appendix A.2) instead of in a */
+
+/* Run configuration (Section 2 and Appendix A.3).  Plain data, copied by
+ * cola_plan_create. */
+typedef struct {
+  int32_t np;       /* particles per side; supported: 16 24 32 48 64 96 128 192 256 384 512 768 1024 */
+  int32_t nm;       /* mesh cells per side; same list; nm must be a multiple of np */
+  double box;       /* periodic box side L [Mpc/h], > 0 */
+  double omega_m;   /* matter density today, > 0 */
+  double omega_l;   /* cosmological constant today; curvature = 1 - omega_m - omega_l */
+  double h;         /* H0 / (100 km/s/Mpc), sets the BBKS shape Gamma = omega_m h */
+  double n_s;       /* primordial spectral index */
+  double sigma8;    /* rms linear density in 8 Mpc/h top-hat spheres at a = 1, > 0 */
+  double a_init;    /* initial scale factor (0.1 is z = 9), 0 < a_init < a_final */
+  double a_final;   /* final scale factor (1 is z = 0) */
+  int32_t n_steps;  /* number of COLA steps (10), >= 1 */
+  double n_lpt;     /* u(a) = a^n_lpt of eq. (KDKALC) (-2.5), != 0 */
+  uint32_t flags;   /* COLA_FLAG_* */
+} cola_config;
+
+typedef struct cola_plan_s *cola_plan;
+
+/* Device particle arrays, each [3][np^3] floats (layout above), caller-owned. */
+typedef struct {
+  float *s;   /* displacement s = x - q */
+  float *v;   /* residual velocity v_res */
+  float *s1;  /* Zel'dovich displacement at a = 1 */
+  float *s2;  /* second-order displacement at a = 1 */
+} cola_particles;
+
+/* Builds a plan: validates cfg and computes in FP64 on the host the growth factors
+ * D1, D2, T[D1], T[D2], T^2[D1], T^2[D2] (Appendix A.1 and A.3), the kick and drift
+ * factors of eq. (KDKALC) on the time grid of eq. (ALCtimestep), the BBKS spectrum
+ * normalised to sigma8, and the FFT twiddles.  Host-only: needs no GPU.
+ * *out receives the plan (NULL on failure). */
+int cola_plan_create(const cola_config *cfg, cola_plan *out);
+
+/* Frees the plan and the device tables it uploaded.  NULL is accepted. */
+int cola_plan_destroy(cola_plan plan);
+
+/* Bytes of workspace every call below needs: max(3 nm^3, np^3) * 4. */
+int cola_workspace_bytes(cola_plan plan, size_t *bytes);
+
+/* Host copy of the per-step scalars (FP64).  out receives n = 13 * (n_steps + 1)
+ * doubles: for i = 0..n_steps the row
+ *   a_i, D1, D2, T[D1], T[D2], T^2[D1], T^2[D2] (all at a_i),
+ *   alpha_i  merged kick factor at a_i (eq. KDKALC; half-kicks at i = 0 and i = n),
+ *   beta_i   drift factor of step i (0 for i = n),
+ *   dD1_i, dD2_i  D1(a_{i+1}) - D1(a_i), D2(a_{i+1}) - D2(a_i) (0 for i = n),
+ *   a_{i+1/2} (0 for i = n), force factor (3/2) Om a_i.
+ * len is the capacity of out in doubles.  Host-only. */
+int cola_step_table(cola_plan plan, double *out, size_t len);
+
+/* White noise: w[p] ~ N(0,1), p < np^3, from Philox4x32-10 (Salmon et al. 2011)
+ * keyed by seed with counter = p / 4, Box-Muller on the four outputs.  w: device,
+ * np^3 floats. */
+int cola_noise(cola_plan plan, uint64_t seed, float *w, void *stream);
+
+/* 2LPT initial conditions (Section 2; Appendix A.3): from white noise w (device,
+ * np^3 floats, not modified) builds the linear field delta_k = w_k sqrt(P(k)/dp^3)
+ * (dp = box/np, BBKS P at a = 1), writes s1 = -grad phi and s2 = grad phi2 with
+ * lap phi = delta, lap phi2 = sum_{i<j} (phi_ii phi_jj - phi_ij^2), then the
+ * initial state s = D1(a_init) s1 + D2(a_init) s2 and v = 0 (the 2LPT velocity
+ * removed by L-(a_init), eq. Lops).  Writes all four arrays of p. */
+int cola_init_2lpt(cola_plan plan, const float *w, const cola_particles *p, void *ws, void *stream);
+
+/* Mean-1 CIC density of the particles at q + s: rho (device, nm^3 floats). */
+int cola_density(cola_plan plan, const float *s, float *rho, void *ws, void *stream);
+
+/* PM force of eq. (eom) at scale factor a: acc = -(3/2) Om a d d^-2 delta
+ * interpolated to each particle (device, [3][np^3] floats). */
+int cola_pm_force(cola_plan plan, const float *s, double a, float *acc, void *ws, void *stream);
+
+/* One COLA step i (0 <= i < n_steps): the kick at a_i (merged half-kicks,
+ * eq. KDKALC with a_c = a_i) using the PM force of the current s, then the drift
+ * to a_{i+1} with a_c = a_{i+1/2}.  In: s(a_i), v(a_{i-1/2}) (v(a_0) for i = 0).
+ * Out, in place: s(a_{i+1}), v(a_{i+1/2}). */
+int cola_step(cola_plan plan, int32_t i, const cola_particles *p, void *ws, void *stream);
+
+/* Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops).  p->v is updated
+ * to v_res(a_n); x_out (device, [3][np^3]) receives the positions (q + s) mod box
+ * and v_out (device, [3][np^3]) the full velocity v_res + T[D1] s1 + T[D2] s2. */
+int cola_finish(cola_plan plan, const cola_particles *p, float *x_out, float *v_out, void *ws, void *stream);
+
+/* Whole run: cola_init_2lpt, cola_step for i = 0..n_steps-1, cola_finish. */
+int cola_run(cola_plan plan, const float *w, const cola_particles *p, float *x_out, float *v_out, void *ws,
+             void *stream);
+
+/* Forward 3D real FFT on an n^3 grid, n = the plan's np or nm: out[kx][ky][kz]
+ * (complex interleaved, kz = 0..n/2-1; the kz = n/2 plane is not produced) =
+ * sum_x in[x] exp(-2 pi i k.x / n).  in, out: device, n^3 floats each (out holds
+ * n * n * (n/2) complex); in is not modified; in == out is allowed. */
+int cola_fft_r2c(cola_plan plan, int32_t n, const float *in, float *out, void *stream);
+
+/* Inverse of cola_fft_r2c with the kz = n/2 plane taken as zero and the 1/n^3
+ * factor applied (numpy irfftn of the padded half spectrum).  in is not modified
+ * unless in == out. */
+int cola_fft_c2r(cola_plan plan, int32_t n, const float *in, float *out, void *stream);
+
+/* Stage tracing (for profiling; off by default).  When enabled, every kernel launch
+ * of the calls above is bracketed by a pair of hipEvents recorded on the launch
+ * stream.  cola_trace_read waits for the recorded events, fills ms[k] with the
+ * summed elapsed milliseconds and launches[k] with the launch count of stage k
+ * (k < cola_trace_stage_count(); n is the capacity of both arrays, which must be at
+ * least that count) and clears the record.  Enabling or disabling clears it too.
+ * Events are created on demand and reused; the calls above stay allocation-free
+ * for device memory. */
+int cola_trace_enable(cola_plan plan, int enable);
+int cola_trace_read(cola_plan plan, double *ms, int32_t *launches, int32_t n);
+int32_t cola_trace_stage_count(void);
+/* Name of stage k (e.g. "fft_y_inv"), or NULL when k is out of range. */
+const char *cola_trace_stage_name(int32_t stage);
+
+const char *cola_strerror(int status);
+int cola_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COLA_H */

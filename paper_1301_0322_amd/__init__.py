@@ -1,0 +1,258 @@
+"""Python binding of the MI355X COLA particle-mesh library (``include/cola.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libcola_mi355x.so``.  Device buffers are torch tensors on the current HIP device;
+work is enqueued on ``torch.cuda.current_stream()``.  There is no CPU fallback:
+if the library is missing every call raises ``RuntimeError``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcola_mi355x.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "cola.h")
+
+COLA_OK = 0
+COLA_FLAG_KDK_STD = 0x1
+COLA_FLAG_NO_LPT_FRAME = 0x2
+COLA_FLAG_LOG_A_STEPS = 0x4
+
+SUPPORTED_SIZES = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
+STEP_TABLE_COLUMNS = ("a", "D1", "D2", "TD1", "TD2", "T2D1", "T2D2", "alpha", "beta",
+                      "dD1", "dD2", "a_mid", "force")
+
+
+class ColaConfig(ctypes.Structure):
+    _fields_ = [
+        ("np", ctypes.c_int32), ("nm", ctypes.c_int32), ("box", ctypes.c_double),
+        ("omega_m", ctypes.c_double), ("omega_l", ctypes.c_double), ("h", ctypes.c_double),
+        ("n_s", ctypes.c_double), ("sigma8", ctypes.c_double), ("a_init", ctypes.c_double),
+        ("a_final", ctypes.c_double), ("n_steps", ctypes.c_int32), ("n_lpt", ctypes.c_double),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class ColaParticles(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_void_p), ("v", ctypes.c_void_p), ("s1", ctypes.c_void_p),
+                ("s2", ctypes.c_void_p)]
+
+
+_VP = ctypes.c_void_p
+_PROTOS = {
+    "cola_plan_create": (ctypes.c_int, [ctypes.POINTER(ColaConfig), ctypes.POINTER(_VP)]),
+    "cola_plan_destroy": (ctypes.c_int, [_VP]),
+    "cola_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "cola_step_table": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    "cola_noise": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
+    "cola_init_2lpt": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP]),
+    "cola_density": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "cola_pm_force": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP]),
+    "cola_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ColaParticles), _VP, _VP]),
+    "cola_finish": (ctypes.c_int, [_VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP]),
+    "cola_run": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP]),
+    "cola_fft_r2c": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "cola_fft_c2r": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "cola_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
+    "cola_trace_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_int32]),
+    "cola_trace_stage_count": (ctypes.c_int32, []),
+    "cola_trace_stage_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "cola_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "cola_last_hip_error": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded shared library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1301_0322_amd/build.py "
+                               "(or __graft_entry__.build()); there is no fallback path")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+class ColaError(RuntimeError):
+    def __init__(self, name: str, status: int):
+        msg = lib().cola_strerror(status).decode()
+        if status == -4:
+            msg += f" (hipError_t {lib().cola_last_hip_error()})"
+        super().__init__(f"{name} failed with status {status}: {msg}")
+        self.status = status
+
+
+def _check(name: str, status: int):
+    if status != COLA_OK:
+        raise ColaError(name, status)
+
+
+def _ptr(t) -> int:
+    if t is None:
+        return 0
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("device buffers must be contiguous")
+        return t.data_ptr()
+    return int(t)
+
+
+def _stream(stream=None) -> int:
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+@dataclass
+class Config:
+    """Mirror of ``cola_config`` with the defaults of the paper's run (Section 2)."""
+    np: int = 32
+    nm: int = 64
+    box: float = 100.0
+    omega_m: float = 0.3
+    omega_l: float = 0.7
+    h: float = 0.7
+    n_s: float = 0.96
+    sigma8: float = 0.8
+    a_init: float = 0.1
+    a_final: float = 1.0
+    n_steps: int = 10
+    n_lpt: float = -2.5
+    flags: int = 0
+
+    def to_c(self) -> ColaConfig:
+        return ColaConfig(self.np, self.nm, self.box, self.omega_m, self.omega_l, self.h, self.n_s,
+                          self.sigma8, self.a_init, self.a_final, self.n_steps, self.n_lpt, self.flags)
+
+
+@dataclass
+class Particles:
+    """Device particle arrays, each a contiguous float32 tensor of shape (3, np^3)."""
+    s: object
+    v: object
+    s1: object
+    s2: object
+
+    @staticmethod
+    def empty(np_side: int, device="cuda"):
+        import torch
+        n = np_side**3
+        mk = lambda: torch.empty((3, n), dtype=torch.float32, device=device)
+        return Particles(mk(), mk(), mk(), mk())
+
+    def to_c(self) -> ColaParticles:
+        return ColaParticles(_ptr(self.s), _ptr(self.v), _ptr(self.s1), _ptr(self.s2))
+
+
+class Plan:
+    """Owns a ``cola_plan``; methods are the C entry points of the same names."""
+
+    def __init__(self, cfg: Config):
+        self.cfg = cfg
+        self._c = _VP()
+        _check("cola_plan_create", lib().cola_plan_create(ctypes.byref(cfg.to_c()), ctypes.byref(self._c)))
+
+    def close(self):
+        if self._c:
+            lib().cola_plan_destroy(self._c)
+            self._c = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- host-only -------------------------------------------------------------------
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check("cola_workspace_bytes", lib().cola_workspace_bytes(self._c, ctypes.byref(b)))
+        return b.value
+
+    def step_table(self):
+        """Per-step FP64 scalars as a dict of lists (columns of cola_step_table)."""
+        n = self.cfg.n_steps + 1
+        buf = (ctypes.c_double * (13 * n))()
+        _check("cola_step_table", lib().cola_step_table(self._c, buf, 13 * n))
+        vals = list(buf)
+        return {c: [vals[13 * i + j] for i in range(n)] for j, c in enumerate(STEP_TABLE_COLUMNS)}
+
+    # -- device ----------------------------------------------------------------------
+    def workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.workspace_bytes() // 4, dtype=torch.float32, device=device)
+
+    def noise(self, seed: int, w, stream=None):
+        _check("cola_noise", lib().cola_noise(self._c, seed, _ptr(w), _stream(stream)))
+
+    def init_2lpt(self, w, p: Particles, ws, stream=None):
+        cp = p.to_c()
+        _check("cola_init_2lpt", lib().cola_init_2lpt(self._c, _ptr(w), ctypes.byref(cp), _ptr(ws),
+                                                      _stream(stream)))
+
+    def density(self, s, rho, ws, stream=None):
+        _check("cola_density", lib().cola_density(self._c, _ptr(s), _ptr(rho), _ptr(ws), _stream(stream)))
+
+    def pm_force(self, s, a: float, acc, ws, stream=None):
+        _check("cola_pm_force", lib().cola_pm_force(self._c, _ptr(s), a, _ptr(acc), _ptr(ws),
+                                                    _stream(stream)))
+
+    def step(self, i: int, p: Particles, ws, stream=None):
+        cp = p.to_c()
+        _check("cola_step", lib().cola_step(self._c, i, ctypes.byref(cp), _ptr(ws), _stream(stream)))
+
+    def finish(self, p: Particles, x_out, v_out, ws, stream=None):
+        cp = p.to_c()
+        _check("cola_finish", lib().cola_finish(self._c, ctypes.byref(cp), _ptr(x_out), _ptr(v_out),
+                                                _ptr(ws), _stream(stream)))
+
+    def run(self, w, p: Particles, x_out, v_out, ws, stream=None):
+        cp = p.to_c()
+        _check("cola_run", lib().cola_run(self._c, _ptr(w), ctypes.byref(cp), _ptr(x_out), _ptr(v_out),
+                                          _ptr(ws), _stream(stream)))
+
+    def trace_enable(self, enable: bool = True):
+        _check("cola_trace_enable", lib().cola_trace_enable(self._c, int(enable)))
+
+    def trace_read(self):
+        """{stage name: (milliseconds, launches)} since the last read (waits for the events)."""
+        n = lib().cola_trace_stage_count()
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int32 * n)()
+        _check("cola_trace_read", lib().cola_trace_read(self._c, ms, cnt, n))
+        return {lib().cola_trace_stage_name(k).decode(): (ms[k], cnt[k]) for k in range(n) if cnt[k]}
+
+    def fft_r2c(self, n: int, inp, out, stream=None):
+        _check("cola_fft_r2c", lib().cola_fft_r2c(self._c, n, _ptr(inp), _ptr(out), _stream(stream)))
+
+    def fft_c2r(self, n: int, inp, out, stream=None):
+        _check("cola_fft_c2r", lib().cola_fft_c2r(self._c, n, _ptr(inp), _ptr(out), _stream(stream)))
+
+
+def run(cfg: Config, w, device="cuda"):
+    """Allocate, run the whole COLA evolution from white noise w; returns (x, v, particles)."""
+    import torch
+    plan = Plan(cfg)
+    p = Particles.empty(cfg.np, device)
+    ws = plan.workspace(device)
+    x = torch.empty((3, cfg.np**3), dtype=torch.float32, device=device)
+    v = torch.empty_like(x)
+    plan.run(w, p, x, v, ws)
+    return x, v, p

@@ -1,0 +1,530 @@
+// C ABI of the COLA library: plan construction (host, FP64) and the enqueue-only
+// entry points that drive the gfx950 kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/cola.h"
+#include "cosmology.hpp"
+#include "internal.hpp"
+
+using namespace cola;
+
+struct cola_plan_s {
+  cola_config cfg;
+  Cosmo cosmo;
+  std::vector<StepRow> table;
+  Growth g_init;                  // growth at a_init (true values, any variant)
+  std::vector<float> tw_nm, tw_np;
+  std::vector<float> lpt_tab;     // sqrt(P/dp^3) / (kf n^2 np^3) indexed by n^2
+  // stage tracing (hipEvent pairs around each launch, on the launch stream)
+  bool trace = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<int> ev_stage;       // stage id of event pair k (events 2k, 2k+1)
+  size_t ev_used = 0;              // pairs recorded since the last read
+  // device copies
+  int device = -1;
+  float2* d_tw_nm = nullptr;
+  float2* d_tw_np = nullptr;
+  float* d_lpt_tab = nullptr;
+};
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+int hip_status(hipError_t e) {
+  if (e == hipSuccess) return COLA_OK;
+  g_last_hip = (int)e;
+  return COLA_ERR_HIP;
+}
+
+// Stage ids reported by cola_trace_read.
+enum Stage : int {
+  kStFill = 0, kStDeposit, kStZFwd, kStYFwd, kStXPoisson, kStYInv, kStZInv, kStGatherKickDrift,
+  kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX, kStLptYInv, kStLptZInv, kStLptHessian,
+  kStNoise, kStFft, kNumStages
+};
+const char* const kStageNames[kNumStages] = {
+  "fill", "deposit", "fft_z_fwd", "fft_y_fwd", "fft_x_poisson", "fft_y_inv", "fft_z_inv",
+  "gather_kick_drift", "gather_force", "gather_finish", "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul",
+  "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise", "fft_test"};
+
+// Records an event pair around launch `fn` when tracing is on.
+template <class F>
+hipError_t traced(cola_plan p, int stage, hipStream_t st, F&& fn) {
+  if (!p->trace) return fn();
+  const size_t need = 2 * (p->ev_used + 1);
+  while (p->ev_pool.size() < need) {
+    hipEvent_t e;
+    const hipError_t rc = hipEventCreate(&e);
+    if (rc != hipSuccess) return rc;
+    p->ev_pool.push_back(e);
+  }
+  hipEvent_t e0 = p->ev_pool[2 * p->ev_used], e1 = p->ev_pool[2 * p->ev_used + 1];
+  hipError_t rc = hipEventRecord(e0, st);
+  if (rc != hipSuccess) return rc;
+  rc = fn();
+  if (rc != hipSuccess) return rc;
+  rc = hipEventRecord(e1, st);
+  if (rc != hipSuccess) return rc;
+  if (p->ev_stage.size() <= p->ev_used) p->ev_stage.resize(p->ev_used + 1);
+  p->ev_stage[p->ev_used++] = stage;
+  return hipSuccess;
+}
+
+#define COLA_TRY(expr)                      \
+  do {                                      \
+    const int rc_ = (expr);                 \
+    if (rc_ != COLA_OK) return rc_;         \
+  } while (0)
+#define COLA_HIP(expr) COLA_TRY(hip_status(expr))
+
+std::vector<float> twiddles(int n) {
+  std::vector<float> t(2 * n);
+  for (int m = 0; m < n; ++m) {
+    const double ang = -2.0 * M_PI * (double)m / (double)n;
+    t[2 * m] = (float)std::cos(ang);
+    t[2 * m + 1] = (float)std::sin(ang);
+  }
+  return t;
+}
+
+int validate(const cola_config* c) {
+  if (!c) return COLA_ERR_INVALID;
+  if (!fft_size_supported(c->np) || !fft_size_supported(c->nm)) return COLA_ERR_UNSUPPORTED_SIZE;
+  if (c->nm % c->np) return COLA_ERR_INVALID;
+  if (!(c->box > 0) || !(c->omega_m > 0) || !(c->sigma8 > 0) || !(c->h > 0)) return COLA_ERR_INVALID;
+  if (!(c->a_init > 0) || !(c->a_final > c->a_init)) return COLA_ERR_INVALID;
+  if (c->n_steps < 1 || c->n_steps > 100000) return COLA_ERR_INVALID;
+  if (c->n_lpt == 0.0 || !std::isfinite(c->n_lpt)) return COLA_ERR_INVALID;
+  if (c->flags & ~(uint32_t)(COLA_FLAG_KDK_STD | COLA_FLAG_NO_LPT_FRAME | COLA_FLAG_LOG_A_STEPS))
+    return COLA_ERR_INVALID;
+  // E(a)^2 must stay positive on [a_init, a_final]
+  const double ok = 1.0 - c->omega_m - c->omega_l;
+  for (int i = 0; i <= 64; ++i) {
+    const double a = c->a_init + (c->a_final - c->a_init) * i / 64.0;
+    if (!(c->omega_m / (a * a * a) + ok / (a * a) + c->omega_l > 0)) return COLA_ERR_INVALID;
+  }
+  return COLA_OK;
+}
+
+template <class T>
+int upload(T** dst, const std::vector<float>& src) {
+  COLA_HIP(hipMalloc((void**)dst, src.size() * sizeof(float)));
+  COLA_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(float), hipMemcpyHostToDevice));
+  return COLA_OK;
+}
+
+// Uploads the plan's tables on first use; later calls must come from the same device.
+int ensure_device(cola_plan p) {
+  int dev = 0;
+  COLA_HIP(hipGetDevice(&dev));
+  if (p->device >= 0) return dev == p->device ? COLA_OK : COLA_ERR_DEVICE;
+  COLA_TRY(upload(&p->d_tw_nm, p->tw_nm));
+  COLA_TRY(upload(&p->d_tw_np, p->tw_np));
+  COLA_TRY(upload(&p->d_lpt_tab, p->lpt_tab));
+  p->device = dev;
+  return COLA_OK;
+}
+
+const float2* twiddle_for(cola_plan p, int n) { return n == p->cfg.nm ? p->d_tw_nm : p->d_tw_np; }
+
+inline long cube(long n) { return n * n * n; }
+
+FieldPtrs fields(std::initializer_list<float*> l) {
+  FieldPtrs f{};
+  int i = 0;
+  for (float* x : l) f.p[i++] = reinterpret_cast<float2*>(x);
+  return f;
+}
+
+Lattice lattice(cola_plan p) {
+  Lattice l;
+  l.np = p->cfg.np;
+  l.nm = p->cfg.nm;
+  l.ratio = p->cfg.nm / p->cfg.np;
+  l.inv_dx = (float)(p->cfg.nm / p->cfg.box);
+  l.npart = cube(p->cfg.np);
+  return l;
+}
+
+// Forward y pass (in place) over nf fields of an n^3 half-spectrum layout.
+int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const float2* tw, hipStream_t st) {
+  const long h = n / 2;
+  return hip_status(traced(p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, st); }));
+}
+
+// The force mesh: g_d = (3/2) Om a irfft(i k_d delta_k / k^2), d = 0..2, in
+// ws[0 .. 3 nm^3) as three real nm^3 fields.
+int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st) {
+  const int n = p->cfg.nm;
+  const long r = cube(n);
+  float* g0 = ws;
+  float* g1 = ws + r;
+  float* g2 = ws + 2 * r;
+  const float2* tw = p->d_tw_nm;
+  const Lattice lat = lattice(p);
+  const double ratio = (double)lat.ratio;
+  COLA_HIP(traced(p, kStFill, st, [&] { return launch_fill(g0, r, 0.0f, st); }));
+  COLA_HIP(traced(p, kStDeposit, st,
+                  [&] { return launch_deposit(lat, s, g0, (float)(ratio * ratio * ratio), st); }));
+  COLA_HIP(traced(p, kStZFwd, st,
+                  [&] { return launch_zfwd(n, g0, reinterpret_cast<float2*>(g0), (long)n * n, tw, st); }));
+  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g0}), 1, tw, st));
+  const double kf = 2.0 * M_PI / p->cfg.box;
+  MulArgs m{};
+  m.c = (float)(1.5 * p->cfg.omega_m * a / (kf * (double)r));
+  COLA_HIP(traced(p, kStXPoisson, st, [&] {
+    return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(g0), fields({g0, g1, g2}), 3, m, tw, st);
+  }));
+  COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0, g1, g2}), 3, tw, st));
+  EpiArgs e{};
+  e.scale = 1.0f;
+  COLA_HIP(traced(p, kStZInv, st, [&] {
+    return launch_zinv(n, fields({g0, g1, g2}), fields({g0, g1, g2}), 3, (long)n * n, tw, kEpiStore, e, st);
+  }));
+  return COLA_OK;
+}
+
+GatherArgs gather_args(cola_plan p, float* ws) {
+  const long r = cube(p->cfg.nm);
+  GatherArgs g{};
+  g.g0 = ws;
+  g.g1 = ws + r;
+  g.g2 = ws + 2 * r;
+  return g;
+}
+
+int check_common(cola_plan p, const void* ws) {
+  if (!p || !ws) return COLA_ERR_INVALID;
+  return ensure_device(p);
+}
+
+int check_particles(const cola_particles* q) {
+  if (!q || !q->s || !q->v || !q->s1 || !q->s2) return COLA_ERR_INVALID;
+  return COLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cola_plan_create(const cola_config* cfg, cola_plan* out) {
+  if (!out) return COLA_ERR_INVALID;
+  *out = nullptr;
+  COLA_TRY(validate(cfg));
+  cola_plan p = new (std::nothrow) cola_plan_s();
+  if (!p) return COLA_ERR_INVALID;
+  p->cfg = *cfg;
+  Cosmo& c = p->cosmo;
+  c.omega_m = cfg->omega_m;
+  c.omega_l = cfg->omega_l;
+  c.h = cfg->h;
+  c.n_s = cfg->n_s;
+  c.sigma8 = cfg->sigma8;
+  c.n_lpt = cfg->n_lpt;
+  c.normalise_sigma8();
+  p->table = build_step_table(c, cfg->a_init, cfg->a_final, cfg->n_steps, cfg->flags);
+  p->g_init = p->table[0].g;
+  p->tw_nm = twiddles(cfg->nm);
+  p->tw_np = twiddles(cfg->np);
+  // 2LPT multiplier: sqrt(P(k) / dp^3) / (kf n^2 np^3) at k = kf |n|, per integer n^2.
+  const long h = cfg->np / 2;
+  const long nmax = 3 * h * h;
+  p->lpt_tab.assign(nmax + 1, 0.0f);
+  const double kf = 2.0 * M_PI / cfg->box;
+  const double dp3 = std::pow(cfg->box / cfg->np, 3);
+  const double np3 = (double)cube(cfg->np);
+  for (long q = 1; q <= nmax; ++q) {
+    const double k = kf * std::sqrt((double)q);
+    p->lpt_tab[q] = (float)(std::sqrt(c.power(k) / dp3) / (kf * (double)q * np3));
+  }
+  *out = p;
+  return COLA_OK;
+}
+
+int cola_plan_destroy(cola_plan p) {
+  if (!p) return COLA_OK;
+  for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+  if (p->device >= 0) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(p->device);
+    (void)hipFree(p->d_tw_nm);
+    (void)hipFree(p->d_tw_np);
+    (void)hipFree(p->d_lpt_tab);
+    (void)hipSetDevice(cur);
+  }
+  delete p;
+  return COLA_OK;
+}
+
+int cola_workspace_bytes(cola_plan p, size_t* bytes) {
+  if (!p || !bytes) return COLA_ERR_INVALID;
+  const size_t a = 3 * (size_t)cube(p->cfg.nm), b = (size_t)cube(p->cfg.np);
+  *bytes = (a > b ? a : b) * sizeof(float);
+  return COLA_OK;
+}
+
+int cola_step_table(cola_plan p, double* out, size_t len) {
+  if (!p || !out) return COLA_ERR_INVALID;
+  const int n = p->cfg.n_steps;
+  if (len < (size_t)13 * (n + 1)) return COLA_ERR_INVALID;
+  for (int i = 0; i <= n; ++i) {
+    const StepRow& r = p->table[i];
+    double* o = out + 13 * i;
+    o[0] = r.a;
+    o[1] = r.g.d1;
+    o[2] = r.g.d2;
+    o[3] = r.g.td1;
+    o[4] = r.g.td2;
+    o[5] = r.g.t2d1;
+    o[6] = r.g.t2d2;
+    o[7] = r.alpha;
+    o[8] = r.beta;
+    o[9] = r.dd1;
+    o[10] = r.dd2;
+    o[11] = r.a_mid;
+    o[12] = r.force;
+  }
+  return COLA_OK;
+}
+
+int cola_noise(cola_plan p, uint64_t seed, float* w, void* stream) {
+  if (!p || !w) return COLA_ERR_INVALID;
+  COLA_TRY(ensure_device(p));
+  hipStream_t st = (hipStream_t)stream;
+  return hip_status(traced(p, kStNoise, st, [&] { return launch_noise(seed, w, cube(p->cfg.np), st); }));
+}
+
+int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* ws_, void* stream) {
+  COLA_TRY(check_common(p, ws_));
+  COLA_TRY(check_particles(q));
+  if (!w) return COLA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  const int n = p->cfg.np;
+  const long r = cube(n);
+  float* w0 = static_cast<float*>(ws_);
+  const float2* tw = p->d_tw_np;
+  // delta_k and its derivatives: s1 into q->s1, Hessian into q->s and q->v.
+  COLA_HIP(traced(p, kStLptZFwd, st,
+                  [&] { return launch_zfwd(n, w, reinterpret_cast<float2*>(w0), (long)n * n, tw, st); }));
+  COLA_TRY(ypass(p, kStLptYFwd, n, -1, fields({w0}), 1, tw, st));
+  MulArgs m{};
+  const double kf = 2.0 * M_PI / p->cfg.box;
+  m.kf = (float)kf;
+  m.tab = p->d_lpt_tab;
+  float* s1[3] = {q->s1, q->s1 + r, q->s1 + 2 * r};
+  float* hs[6] = {q->s, q->s + r, q->s + 2 * r, q->v, q->v + r, q->v + 2 * r};
+  FieldPtrs outs = fields({s1[0], s1[1], s1[2], hs[0], hs[1], hs[2], hs[3], hs[4], hs[5]});
+  COLA_HIP(traced(p, kStLptX, st,
+                  [&] { return launch_xmul(n, kMulLpt1, reinterpret_cast<float2*>(w0), outs, 9, m, tw, st); }));
+  COLA_TRY(ypass(p, kStLptYInv, n, 1, outs, 9, tw, st));
+  EpiArgs e{};
+  e.scale = 1.0f;
+  FieldPtrs f_s1 = fields({s1[0], s1[1], s1[2]});
+  COLA_HIP(traced(p, kStLptZInv, st,
+                  [&] { return launch_zinv(n, f_s1, f_s1, 3, (long)n * n, tw, kEpiStore, e, st); }));
+  COLA_HIP(traced(p, kStLptHessian, st, [&] {
+    return launch_zinv_hessian(n, fields({hs[0], hs[1], hs[2], hs[3], hs[4], hs[5]}), w0, (long)n * n, tw, 1.0f,
+                               st);
+  }));
+  // second order: s2_k = -i k S_k / k^2
+  COLA_HIP(traced(p, kStLptZFwd, st,
+                  [&] { return launch_zfwd(n, w0, reinterpret_cast<float2*>(w0), (long)n * n, tw, st); }));
+  COLA_TRY(ypass(p, kStLptYFwd, n, -1, fields({w0}), 1, tw, st));
+  float* s2[3] = {q->s2, q->s2 + r, q->s2 + 2 * r};
+  FieldPtrs f_s2 = fields({s2[0], s2[1], s2[2]});
+  MulArgs m2{};
+  m2.c = (float)(-1.0 / (kf * (double)r));
+  COLA_HIP(traced(p, kStLptX, st,
+                  [&] { return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(w0), f_s2, 3, m2, tw, st); }));
+  COLA_TRY(ypass(p, kStLptYInv, n, 1, f_s2, 3, tw, st));
+  // s2, then s = D1 s1 + D2 s2 and the initial velocity.
+  EpiArgs ef{};
+  ef.scale = 1.0f;
+  ef.d1 = (float)p->g_init.d1;
+  ef.d2 = (float)p->g_init.d2;
+  ef.s1 = q->s1;
+  ef.s = q->s;
+  ef.v = q->v;
+  ef.comp_stride = r;
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  ef.v1 = plain ? (float)p->g_init.td1 : 0.0f;   // L-(a_init) cancels the 2LPT velocity
+  ef.v2 = plain ? (float)p->g_init.td2 : 0.0f;
+  COLA_HIP(traced(p, kStLptZInv, st,
+                  [&] { return launch_zinv(n, f_s2, f_s2, 3, (long)n * n, tw, kEpiLptFinal, ef, st); }));
+  return COLA_OK;
+}
+
+int cola_density(cola_plan p, const float* s, float* rho, void* ws, void* stream) {
+  COLA_TRY(check_common(p, ws));
+  if (!s || !rho) return COLA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  const Lattice lat = lattice(p);
+  const double ratio = (double)lat.ratio;
+  COLA_HIP(traced(p, kStFill, st, [&] { return launch_fill(rho, cube(p->cfg.nm), 0.0f, st); }));
+  COLA_HIP(traced(p, kStDeposit, st,
+                  [&] { return launch_deposit(lat, s, rho, (float)(ratio * ratio * ratio), st); }));
+  return COLA_OK;
+}
+
+int cola_pm_force(cola_plan p, const float* s, double a, float* acc, void* ws_, void* stream) {
+  COLA_TRY(check_common(p, ws_));
+  if (!s || !acc || !(a > 0)) return COLA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  float* ws = static_cast<float*>(ws_);
+  COLA_TRY(pm_mesh(p, s, a, ws, st));
+  GatherArgs g = gather_args(p, ws);
+  g.s = const_cast<float*>(s);
+  g.out_a = acc;
+  return hip_status(
+      traced(p, kStGatherForce, st, [&] { return launch_gather(lattice(p), kGatherForce, g, KickArgs{}, st); }));
+}
+
+int cola_step(cola_plan p, int32_t i, const cola_particles* q, void* ws_, void* stream) {
+  COLA_TRY(check_common(p, ws_));
+  COLA_TRY(check_particles(q));
+  if (i < 0 || i >= p->cfg.n_steps) return COLA_ERR_RANGE;
+  hipStream_t st = (hipStream_t)stream;
+  float* ws = static_cast<float*>(ws_);
+  const StepRow& row = p->table[i];
+  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st));
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  KickArgs k{};
+  k.alpha = (float)row.alpha;
+  k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
+  k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
+  k.beta = (float)row.beta;
+  k.dd1 = plain ? 0.0f : (float)row.dd1;
+  k.dd2 = plain ? 0.0f : (float)row.dd2;
+  GatherArgs g = gather_args(p, ws);
+  g.s = q->s;
+  g.v = q->v;
+  g.s1 = q->s1;
+  g.s2 = q->s2;
+  return hip_status(
+      traced(p, kStGatherKickDrift, st, [&] { return launch_gather(lattice(p), kGatherKickDrift, g, k, st); }));
+}
+
+int cola_finish(cola_plan p, const cola_particles* q, float* x_out, float* v_out, void* ws_, void* stream) {
+  COLA_TRY(check_common(p, ws_));
+  COLA_TRY(check_particles(q));
+  if (!x_out || !v_out) return COLA_ERR_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  float* ws = static_cast<float*>(ws_);
+  const StepRow& row = p->table[p->cfg.n_steps];
+  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st));
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  KickArgs k{};
+  k.alpha = (float)row.alpha;
+  k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
+  k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
+  k.td1 = plain ? 0.0f : (float)row.g.td1;
+  k.td2 = plain ? 0.0f : (float)row.g.td2;
+  k.box = (float)p->cfg.box;
+  GatherArgs g = gather_args(p, ws);
+  g.s = q->s;
+  g.v = q->v;
+  g.s1 = q->s1;
+  g.s2 = q->s2;
+  g.out_a = x_out;
+  g.out_b = v_out;
+  return hip_status(traced(p, kStFinish, st, [&] { return launch_gather(lattice(p), kGatherFinish, g, k, st); }));
+}
+
+int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out, float* v_out, void* ws,
+             void* stream) {
+  COLA_TRY(cola_init_2lpt(p, w, q, ws, stream));
+  for (int i = 0; i < p->cfg.n_steps; ++i) COLA_TRY(cola_step(p, i, q, ws, stream));
+  return cola_finish(p, q, x_out, v_out, ws, stream);
+}
+
+int cola_fft_r2c(cola_plan p, int32_t n, const float* in, float* out, void* stream) {
+  if (!p || !in || !out) return COLA_ERR_INVALID;
+  if (n != p->cfg.nm && n != p->cfg.np) return COLA_ERR_INVALID;
+  COLA_TRY(ensure_device(p));
+  hipStream_t st = (hipStream_t)stream;
+  const float2* tw = twiddle_for(p, n);
+  COLA_HIP(traced(p, kStFft, st,
+                  [&] { return launch_zfwd(n, in, reinterpret_cast<float2*>(out), (long)n * n, tw, st); }));
+  COLA_TRY(ypass(p, kStFft, n, -1, fields({out}), 1, tw, st));
+  const long h = n / 2;
+  FieldPtrs f = fields({out});
+  return hip_status(
+      traced(p, kStFft, st, [&] { return launch_col(n, -1, f, f, 1, n, h, (long)n * h, (int)h, tw, st); }));
+}
+
+int cola_fft_c2r(cola_plan p, int32_t n, const float* in, float* out, void* stream) {
+  if (!p || !in || !out) return COLA_ERR_INVALID;
+  if (n != p->cfg.nm && n != p->cfg.np) return COLA_ERR_INVALID;
+  COLA_TRY(ensure_device(p));
+  hipStream_t st = (hipStream_t)stream;
+  const float2* tw = twiddle_for(p, n);
+  const long h = n / 2;
+  FieldPtrs fi = fields({const_cast<float*>(in)});
+  FieldPtrs fo = fields({out});
+  COLA_HIP(traced(p, kStFft, st, [&] { return launch_col(n, 1, fi, fo, 1, n, h, (long)n * h, (int)h, tw, st); }));
+  COLA_TRY(ypass(p, kStFft, n, 1, fo, 1, tw, st));
+  EpiArgs e{};
+  e.scale = (float)(1.0 / (double)cube(n));
+  return hip_status(
+      traced(p, kStFft, st, [&] { return launch_zinv(n, fo, fo, 1, (long)n * n, tw, kEpiStore, e, st); }));
+}
+
+int cola_trace_enable(cola_plan p, int enable) {
+  if (!p) return COLA_ERR_INVALID;
+  p->trace = enable != 0;
+  p->ev_used = 0;
+  return COLA_OK;
+}
+
+int cola_trace_read(cola_plan p, double* ms, int32_t* launches, int32_t n) {
+  if (!p || !ms || !launches || n < kNumStages) return COLA_ERR_INVALID;
+  for (int k = 0; k < kNumStages; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (size_t j = 0; j < p->ev_used; ++j) {
+    COLA_HIP(hipEventSynchronize(p->ev_pool[2 * j + 1]));
+    float t = 0.f;
+    COLA_HIP(hipEventElapsedTime(&t, p->ev_pool[2 * j], p->ev_pool[2 * j + 1]));
+    ms[p->ev_stage[j]] += t;
+    launches[p->ev_stage[j]] += 1;
+  }
+  p->ev_used = 0;
+  return COLA_OK;
+}
+
+const char* cola_trace_stage_name(int32_t stage) {
+  return (stage >= 0 && stage < kNumStages) ? kStageNames[stage] : nullptr;
+}
+
+int32_t cola_trace_stage_count(void) { return kNumStages; }
+
+const char* cola_strerror(int status) {
+  switch (status) {
+    case COLA_OK:
+      return "success";
+    case COLA_ERR_INVALID:
+      return "invalid argument (null pointer or inconsistent parameter)";
+    case COLA_ERR_UNSUPPORTED_SIZE:
+      return "unsupported size: np and nm must be one of 16 24 32 48 64 96 128 192 256 384 512 768 1024";
+    case COLA_ERR_RANGE:
+      return "step index out of range";
+    case COLA_ERR_HIP:
+      return "HIP runtime error (see cola_last_hip_error)";
+    case COLA_ERR_DEVICE:
+      return "plan tables live on another device";
+    default:
+      return "unknown status";
+  }
+}
+
+int cola_last_hip_error(void) { return g_last_hip; }
+
+}  // extern "C"

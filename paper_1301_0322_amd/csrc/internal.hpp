@@ -1,0 +1,108 @@
+// Internal declarations shared by the host code and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace cola {
+
+constexpr int kMaxFields = 9;
+
+struct FieldPtrs {
+  float2* p[kMaxFields];
+};
+
+// k-space multiplier applied between the forward and inverse x transforms.
+enum MulMode : int {
+  kMulGrad = 0,   // out_j = c * i n_j / n^2 * X            (3 outputs)
+  kMulLpt1 = 1,   // s1_j = i n_j tab[n^2] X, phi_ij = kf n_i n_j tab[n^2] X  (9 outputs)
+};
+
+struct MulArgs {
+  float c;            // kMulGrad scale
+  float kf;           // fundamental wavenumber, kMulLpt1 phi scale
+  const float* tab;   // kMulLpt1 table indexed by n^2
+};
+
+// Epilogue of the inverse z (complex-to-real) pass.
+enum ZinvEpi : int {
+  kEpiStore = 0,      // out = scale * x
+  kEpiLptFinal = 1,   // out = s2_d; s_d = d1 s1_d + d2 s2_d; v_d = v1 s1_d + v2 s2_d
+};
+
+struct EpiArgs {
+  float scale;
+  float d1, d2;
+  float v1, v2;
+  const float* s1;    // component base pointers, advanced by comp_stride per field
+  float* s;
+  float* v;
+  long comp_stride;
+};
+
+bool fft_size_supported(int n);
+
+// Forward real-to-complex z pass: rows of n reals -> rows of n/2 complex
+// (modes 0..n/2-1; the n/2 mode is dropped).  in and out may alias.
+hipError_t launch_zfwd(int n, const float* in, float2* out, long nrows, const float2* tw,
+                       hipStream_t st);
+// Inverse complex-to-real z pass for nfields fields; field f reads in.p[f], writes
+// out.p[f] (as float rows).  May alias.
+hipError_t launch_zinv(int n, FieldPtrs in, FieldPtrs out, int nfields, long nrows,
+                       const float2* tw, int epi, EpiArgs epi_args, hipStream_t st);
+// Inverse z pass over the six Hessian fields (xx, yy, zz, xy, yz, zx) writing the
+// second-order source S = sum_{i<j} (phi_ii phi_jj - phi_ij^2) as real rows.
+hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, const float2* tw,
+                               float scale, hipStream_t st);
+// Strided column pass (length n along inner_stride) over tiles of contiguous columns.
+// Tiles: outer index o in [0, n_outer) at outer_stride; columns [0, ncols) contiguous.
+hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, int n_outer,
+                      long outer_stride, long inner_stride, int ncols, const float2* tw,
+                      hipStream_t st);
+// x pass with the k-space multiplier: forward x transform of `in`, multiply, inverse
+// x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row.
+hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m,
+                       const float2* tw, hipStream_t st);
+
+// Particle kernels.
+struct Lattice {
+  int np;           // particles per side
+  int nm;           // mesh cells per side
+  int ratio;        // nm / np
+  float inv_dx;     // nm / L
+  long npart;       // np^3
+};
+
+hipError_t launch_fill(float* p, long n, float value, hipStream_t st);
+hipError_t launch_deposit(Lattice lat, const float* s, float* rho, float mass, hipStream_t st);
+
+struct KickArgs {
+  float alpha;                 // kick factor
+  float t2d1, t2d2;            // T^2[D1](a_c), T^2[D2](a_c)
+  float beta;                  // drift factor (do_drift)
+  float dd1, dd2;              // D1, D2 increments (do_drift)
+  float td1, td2;              // T[D1](a_n), T[D2](a_n) for L+ (finish)
+  float box;
+};
+enum GatherMode : int {
+  kGatherForce = 0,     // acc_d = F_d
+  kGatherKickDrift = 1, // v += alpha (F - t2d1 s1 - t2d2 s2); s += beta v + dd1 s1 + dd2 s2
+  kGatherFinish = 2,    // kick, then x = (q + s) mod L, v_out = v + td1 s1 + td2 s2
+};
+struct GatherArgs {
+  const float* g0;
+  const float* g1;
+  const float* g2;
+  float* s;
+  float* v;
+  const float* s1;
+  const float* s2;
+  float* out_a;     // kGatherForce: acc; kGatherFinish: x
+  float* out_b;     // kGatherFinish: v_phys
+};
+hipError_t launch_gather(Lattice lat, int mode, GatherArgs a, KickArgs k, hipStream_t st);
+
+hipError_t launch_noise(uint64_t seed, float* w, long count, hipStream_t st);
+
+}  // namespace cola

@@ -1,0 +1,70 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry
+point, validates configurations, and its FP64 host tables agree with the oracle."""
+import ctypes
+import re
+
+import numpy as np
+import pytest
+
+import paper_1301_0322_amd as cola
+from oracle import cosmology as cosmo
+
+
+def _declared_functions():
+    text = open(cola.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cola_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cola.lib()
+    names = _declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    # and the binding wraps each of them
+    assert set(names) == set(cola._PROTOS)
+
+
+def test_plan_validation():
+    with pytest.raises(cola.ColaError) as e:
+        cola.Plan(cola.Config(np=20, nm=40))
+    assert e.value.status == -2
+    with pytest.raises(cola.ColaError):
+        cola.Plan(cola.Config(np=32, nm=48))        # nm not a multiple of np
+    with pytest.raises(cola.ColaError):
+        cola.Plan(cola.Config(n_lpt=0.0))
+    with pytest.raises(cola.ColaError):
+        cola.Plan(cola.Config(a_init=1.0, a_final=0.5))
+    with pytest.raises(cola.ColaError):
+        cola.Plan(cola.Config(n_steps=0))
+    with pytest.raises(cola.ColaError):
+        cola.Plan(cola.Config(flags=0x80))
+    assert cola.lib().cola_strerror(-2).decode().startswith("unsupported size")
+
+
+def test_workspace_size():
+    with cola.Plan(cola.Config(np=32, nm=64)) as p:
+        assert p.workspace_bytes() == 3 * 64**3 * 4
+    with cola.Plan(cola.Config(np=64, nm=64)) as p:
+        assert p.workspace_bytes() == 3 * 64**3 * 4
+
+
+@pytest.mark.parametrize("kw", [{}, {"n_steps": 3}, {"omega_m": 0.25, "omega_l": 0.75}, {"n_lpt": 1.5},
+                                {"omega_m": 0.3, "omega_l": 0.6}])
+def test_host_step_table_matches_oracle(kw):
+    cfg = cola.Config(**kw)
+    with cola.Plan(cfg) as p:
+        t = p.step_table()
+    ocfg = cosmo.Config(**{k: v for k, v in kw.items()})
+    ot = cosmo.step_table(ocfg)
+    g = ot.grow
+    np.testing.assert_allclose(t["a"], ot.a, rtol=1e-14)
+    for col in ("D1", "D2", "TD1", "TD2", "T2D1", "T2D2"):
+        np.testing.assert_allclose(t[col], g[col], rtol=1e-9, err_msg=col)
+    np.testing.assert_allclose(t["alpha"], ot.alpha, rtol=1e-10)
+    np.testing.assert_allclose(t["beta"][:-1], ot.beta, rtol=1e-10)
+    np.testing.assert_allclose(t["dD1"][:-1], ot.dD1, rtol=1e-8)
+    np.testing.assert_allclose(t["dD2"][:-1], ot.dD2, rtol=1e-8)
+    np.testing.assert_allclose(t["a_mid"][:-1], ot.a_mid, rtol=1e-14)
+    np.testing.assert_allclose(t["force"], 1.5 * ocfg.omega_m * ot.a, rtol=1e-14)
