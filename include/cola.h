@@ -98,7 +98,10 @@ int cola_plan_create(const cola_config *cfg, cola_plan *out);
 /* Frees the plan and the device tables it uploaded.  NULL is accepted. */
 int cola_plan_destroy(cola_plan plan);
 
-/* Bytes of workspace every call below needs: max(3 nm^3, np^3) * 4. */
+/* Bytes of workspace every call below needs: three nm^3 float meshes, the
+ * per-step particle binning buffers (12 bytes per particle, three int arrays of
+ * one entry per 8x8xtz tile, the halo faces of every tile) and two tile-sorted
+ * copies of the particle state used by cola_run (104 bytes per particle). */
 int cola_workspace_bytes(cola_plan plan, size_t *bytes);
 
 /* Host copy of the per-step scalars (FP64).  out receives n = 13 * (n_steps + 1)
@@ -142,7 +145,11 @@ int cola_step(cola_plan plan, int32_t i, const cola_particles *p, void *ws, void
  * and v_out (device, [3][np^3]) the full velocity v_res + T[D1] s1 + T[D2] s2. */
 int cola_finish(cola_plan plan, const cola_particles *p, float *x_out, float *v_out, void *ws, void *stream);
 
-/* Whole run: cola_init_2lpt, cola_step for i = 0..n_steps-1, cola_finish. */
+/* Whole run: cola_init_2lpt, then the n_steps COLA steps and the closing kick of
+ * cola_step / cola_finish.  Internally the particle state is kept in workspace
+ * copies sorted by mesh tile between force evaluations (same arithmetic, order of
+ * FP32 summation in the deposit aside); on return p holds the final s, v_res (in
+ * Lagrangian order) and the unchanged s1, s2. */
 int cola_run(cola_plan plan, const float *w, const cola_particles *p, float *x_out, float *v_out, void *ws,
              void *stream);
 
@@ -156,6 +163,13 @@ int cola_fft_r2c(cola_plan plan, int32_t n, const float *in, float *out, void *s
  * factor applied (numpy irfftn of the padded half spectrum).  in is not modified
  * unless in == out. */
 int cola_fft_c2r(cola_plan plan, int32_t n, const float *in, float *out, void *stream);
+
+/* Tile shape of the strided FFT passes on the nm^3 mesh (a tuning knob; results
+ * are identical for every valid shape).  pass 0 = the y passes, 1 = the x pass
+ * with the Poisson multiplier; width = columns per tile, one of 4, 8, 16, or 0 for
+ * the built-in default.  COLA_ERR_UNSUPPORTED_SIZE if the width does not divide
+ * nm/2 or the tile would exceed 64 KB of LDS.  Host-only. */
+int cola_plan_set_fft_tile(cola_plan plan, int32_t pass, int32_t width);
 
 /* Stage tracing (for profiling; off by default).  When enabled, every kernel launch
  * of the calls above is bracketed by a pair of hipEvents recorded on the launch

@@ -55,6 +55,7 @@ _PROTOS = {
     "cola_run": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP]),
     "cola_fft_r2c": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "cola_fft_c2r": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
+    "cola_plan_set_fft_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "cola_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "cola_trace_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_int32]),
@@ -227,6 +228,9 @@ class Plan:
         cp = p.to_c()
         _check("cola_run", lib().cola_run(self._c, _ptr(w), ctypes.byref(cp), _ptr(x_out), _ptr(v_out),
                                           _ptr(ws), _stream(stream)))
+
+    def set_fft_tile(self, pass_: int, width: int):
+        _check("cola_plan_set_fft_tile", lib().cola_plan_set_fft_tile(self._c, pass_, width))
 
     def trace_enable(self, enable: bool = True):
         _check("cola_trace_enable", lib().cola_trace_enable(self._c, int(enable)))

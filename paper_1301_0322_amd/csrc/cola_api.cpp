@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "../../include/cola.h"
@@ -20,6 +21,8 @@ struct cola_plan_s {
   Growth g_init;                  // growth at a_init (true values, any variant)
   std::vector<float> tw_nm, tw_np;
   std::vector<float> lpt_tab;     // sqrt(P/dp^3) / (kf n^2 np^3) indexed by n^2
+  Bins bins;                      // Eulerian tiles of the force mesh
+  int fft_width[2] = {0, 0};      // columns per tile of the mesh-size y passes and x pass (0: default)
   // stage tracing (hipEvent pairs around each launch, on the launch stream)
   bool trace = false;
   std::vector<hipEvent_t> ev_pool;
@@ -44,14 +47,15 @@ int hip_status(hipError_t e) {
 
 // Stage ids reported by cola_trace_read.
 enum Stage : int {
-  kStFill = 0, kStDeposit, kStZFwd, kStYFwd, kStXPoisson, kStYInv, kStZInv, kStGatherKickDrift,
-  kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX, kStLptYInv, kStLptZInv, kStLptHessian,
-  kStNoise, kStFft, kNumStages
+  kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStDepositMerge, kStZFwd, kStYFwd, kStXPoisson,
+  kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
+  kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
-  "fill", "deposit", "fft_z_fwd", "fft_y_fwd", "fft_x_poisson", "fft_y_inv", "fft_z_inv",
-  "gather_kick_drift", "gather_force", "gather_finish", "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul",
-  "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise", "fft_test"};
+  "bin_count", "bin_scan", "bin_scatter", "deposit", "deposit_merge", "fft_z_fwd", "fft_y_fwd",
+  "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
+  "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
+  "fft_test"};
 
 // Records an event pair around launch `fn` when tracing is on.
 template <class F>
@@ -153,25 +157,76 @@ Lattice lattice(cola_plan p) {
 }
 
 // Forward y pass (in place) over nf fields of an n^3 half-spectrum layout.
+int width_for(cola_plan p, int n, int pass) { return n == p->cfg.nm ? p->fft_width[pass] : 0; }
+
 int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const float2* tw, hipStream_t st) {
   const long h = n / 2;
-  return hip_status(traced(p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, st); }));
+  const int w = width_for(p, n, 0);
+  return hip_status(
+      traced(p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, w, st); }));
+}
+
+// Workspace: three real nm^3 meshes, then the binning buffers.
+size_t mesh_floats(cola_plan p) { return 3 * (size_t)cube(p->cfg.nm); }
+
+// parity selects which of the two tile-count arrays holds the current counts
+// (cola_run alternates them: a step's gather counts into the other one).
+BinBuffers bin_buffers(cola_plan p, float* ws, int parity = 0) {
+  BinBuffers bb = carve_bins(ws + mesh_floats(p), cube(p->cfg.np), p->bins);
+  if (parity) std::swap(bb.count, bb.count_next);
+  return bb;
+}
+
+// Two tile-sorted copies of the particle state (13 words per particle each) after
+// the binning buffers; used by cola_run.
+SortedState sorted_state(cola_plan p, float* ws, int which) {
+  const long n = cube(p->cfg.np);
+  char* c = reinterpret_cast<char*>(ws + mesh_floats(p)) + bin_workspace_bytes(n, p->bins);
+  float* f = reinterpret_cast<float*>(c) + (long)which * 13 * n;
+  SortedState ss;
+  ss.s = f;
+  ss.v = f + 3 * n;
+  ss.s1 = f + 6 * n;
+  ss.s2 = f + 9 * n;
+  ss.lag = reinterpret_cast<int*>(f + 12 * n);
+  return ss;
+}
+
+// How a PM force evaluation obtains its particle bins.
+struct BinPlan {
+  bool prebinned = false;   // counts and ranks already produced by the previous gather
+  bool bin_next = false;    // this step's gather bins the drifted particles
+  int parity = 0;
+};
+
+// Bins the particles at q + s by Eulerian tile (unless prebinned) and deposits
+// their CIC density (mean 1) into rho; the bins stay valid for a gather from the
+// same s.
+int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t st, BinPlan bp = {}) {
+  const Lattice lat = lattice(p);
+  const Bins& b = p->bins;
+  const BinBuffers bb = bin_buffers(p, ws, bp.parity);
+  const double ratio = (double)lat.ratio;
+  if (!bp.prebinned) COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, s, bb, st); }));
+  COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, bp.bin_next, st); }));
+  COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
+  COLA_HIP(traced(p, kStDeposit, st,
+                  [&] { return launch_deposit(lat, b, s, bb, rho, (float)(ratio * ratio * ratio), st); }));
+  COLA_HIP(traced(p, kStDepositMerge, st, [&] { return launch_deposit_merge(lat, b, bb, rho, st); }));
+  return COLA_OK;
 }
 
 // The force mesh: g_d = (3/2) Om a irfft(i k_d delta_k / k^2), d = 0..2, in
 // ws[0 .. 3 nm^3) as three real nm^3 fields.
-int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st) {
+// Poisson solve on the density in ws mesh 0: g_d = (3/2) Om a irfft(i k_d delta_k / k^2),
+// d = 0..2, left in the three ws meshes.
+int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   const int n = p->cfg.nm;
   const long r = cube(n);
   float* g0 = ws;
   float* g1 = ws + r;
   float* g2 = ws + 2 * r;
   const float2* tw = p->d_tw_nm;
-  const Lattice lat = lattice(p);
-  const double ratio = (double)lat.ratio;
-  COLA_HIP(traced(p, kStFill, st, [&] { return launch_fill(g0, r, 0.0f, st); }));
-  COLA_HIP(traced(p, kStDeposit, st,
-                  [&] { return launch_deposit(lat, s, g0, (float)(ratio * ratio * ratio), st); }));
   COLA_HIP(traced(p, kStZFwd, st,
                   [&] { return launch_zfwd(n, g0, reinterpret_cast<float2*>(g0), (long)n * n, tw, st); }));
   COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g0}), 1, tw, st));
@@ -179,7 +234,8 @@ int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st) {
   MulArgs m{};
   m.c = (float)(1.5 * p->cfg.omega_m * a / (kf * (double)r));
   COLA_HIP(traced(p, kStXPoisson, st, [&] {
-    return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(g0), fields({g0, g1, g2}), 3, m, tw, st);
+    return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(g0), fields({g0, g1, g2}), 3, m, tw,
+                       p->fft_width[1], st);
   }));
   COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0, g1, g2}), 3, tw, st));
   EpiArgs e{};
@@ -188,6 +244,12 @@ int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st) {
     return launch_zinv(n, fields({g0, g1, g2}), fields({g0, g1, g2}), 3, (long)n * n, tw, kEpiStore, e, st);
   }));
   return COLA_OK;
+}
+
+// The force mesh of particles at q + s (binning them first unless prebinned).
+int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st, BinPlan bp = {}) {
+  COLA_TRY(deposit_into(p, s, ws, ws, st, bp));
+  return fft_force(p, a, ws, st);
 }
 
 GatherArgs gather_args(cola_plan p, float* ws) {
@@ -207,6 +269,53 @@ int check_common(cola_plan p, const void* ws) {
 int check_particles(const cola_particles* q) {
   if (!q || !q->s || !q->v || !q->s1 || !q->s2) return COLA_ERR_INVALID;
   return COLA_OK;
+}
+
+// One COLA step: PM force at a_i, merged kick, drift (eq. KDKALC).
+int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st, BinPlan bp) {
+  const StepRow& row = p->table[i];
+  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st, bp));
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  KickArgs k{};
+  k.alpha = (float)row.alpha;
+  k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
+  k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
+  k.beta = (float)row.beta;
+  k.dd1 = plain ? 0.0f : (float)row.dd1;
+  k.dd2 = plain ? 0.0f : (float)row.dd2;
+  GatherArgs g = gather_args(p, ws);
+  g.s = q->s;
+  g.v = q->v;
+  g.s1 = q->s1;
+  g.s2 = q->s2;
+  return hip_status(traced(p, kStGatherKickDrift, st, [&] {
+    return launch_gather(lattice(p), p->bins, bin_buffers(p, ws, bp.parity), kGatherKickDrift, bp.bin_next, g, k, st);
+  }));
+}
+
+// Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops).
+int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out, float* ws, hipStream_t st,
+                BinPlan bp) {
+  const StepRow& row = p->table[p->cfg.n_steps];
+  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st, bp));
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  KickArgs k{};
+  k.alpha = (float)row.alpha;
+  k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
+  k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
+  k.td1 = plain ? 0.0f : (float)row.g.td1;
+  k.td2 = plain ? 0.0f : (float)row.g.td2;
+  k.box = (float)p->cfg.box;
+  GatherArgs g = gather_args(p, ws);
+  g.s = q->s;
+  g.v = q->v;
+  g.s1 = q->s1;
+  g.s2 = q->s2;
+  g.out_a = x_out;
+  g.out_b = v_out;
+  return hip_status(traced(p, kStFinish, st, [&] {
+    return launch_gather(lattice(p), p->bins, bin_buffers(p, ws, bp.parity), kGatherFinish, false, g, k, st);
+  }));
 }
 
 }  // namespace
@@ -230,6 +339,7 @@ int cola_plan_create(const cola_config* cfg, cola_plan* out) {
   c.normalise_sigma8();
   p->table = build_step_table(c, cfg->a_init, cfg->a_final, cfg->n_steps, cfg->flags);
   p->g_init = p->table[0].g;
+  p->bins = make_bins(cfg->nm);
   p->tw_nm = twiddles(cfg->nm);
   p->tw_np = twiddles(cfg->np);
   // 2LPT multiplier: sqrt(P(k) / dp^3) / (kf n^2 np^3) at k = kf |n|, per integer n^2.
@@ -265,8 +375,10 @@ int cola_plan_destroy(cola_plan p) {
 
 int cola_workspace_bytes(cola_plan p, size_t* bytes) {
   if (!p || !bytes) return COLA_ERR_INVALID;
-  const size_t a = 3 * (size_t)cube(p->cfg.nm), b = (size_t)cube(p->cfg.np);
-  *bytes = (a > b ? a : b) * sizeof(float);
+  // 3 nm^3 floats of meshes (np^3 <= nm^3 covers the 2LPT scratch), then the bins
+  const size_t mesh = mesh_floats(p) * sizeof(float);
+  const size_t sorted = 2 * 13 * (size_t)cube(p->cfg.np) * sizeof(float);
+  *bytes = mesh + bin_workspace_bytes(cube(p->cfg.np), p->bins) + sorted;
   return COLA_OK;
 }
 
@@ -322,7 +434,7 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
   float* hs[6] = {q->s, q->s + r, q->s + 2 * r, q->v, q->v + r, q->v + 2 * r};
   FieldPtrs outs = fields({s1[0], s1[1], s1[2], hs[0], hs[1], hs[2], hs[3], hs[4], hs[5]});
   COLA_HIP(traced(p, kStLptX, st,
-                  [&] { return launch_xmul(n, kMulLpt1, reinterpret_cast<float2*>(w0), outs, 9, m, tw, st); }));
+                  [&] { return launch_xmul(n, kMulLpt1, reinterpret_cast<float2*>(w0), outs, 9, m, tw, 0, st); }));
   COLA_TRY(ypass(p, kStLptYInv, n, 1, outs, 9, tw, st));
   EpiArgs e{};
   e.scale = 1.0f;
@@ -342,7 +454,7 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
   MulArgs m2{};
   m2.c = (float)(-1.0 / (kf * (double)r));
   COLA_HIP(traced(p, kStLptX, st,
-                  [&] { return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(w0), f_s2, 3, m2, tw, st); }));
+                  [&] { return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(w0), f_s2, 3, m2, tw, 0, st); }));
   COLA_TRY(ypass(p, kStLptYInv, n, 1, f_s2, 3, tw, st));
   // s2, then s = D1 s1 + D2 s2 and the initial velocity.
   EpiArgs ef{};
@@ -364,13 +476,7 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
 int cola_density(cola_plan p, const float* s, float* rho, void* ws, void* stream) {
   COLA_TRY(check_common(p, ws));
   if (!s || !rho) return COLA_ERR_INVALID;
-  hipStream_t st = (hipStream_t)stream;
-  const Lattice lat = lattice(p);
-  const double ratio = (double)lat.ratio;
-  COLA_HIP(traced(p, kStFill, st, [&] { return launch_fill(rho, cube(p->cfg.nm), 0.0f, st); }));
-  COLA_HIP(traced(p, kStDeposit, st,
-                  [&] { return launch_deposit(lat, s, rho, (float)(ratio * ratio * ratio), st); }));
-  return COLA_OK;
+  return deposit_into(p, s, rho, static_cast<float*>(ws), (hipStream_t)stream);
 }
 
 int cola_pm_force(cola_plan p, const float* s, double a, float* acc, void* ws_, void* stream) {
@@ -383,65 +489,78 @@ int cola_pm_force(cola_plan p, const float* s, double a, float* acc, void* ws_, 
   g.s = const_cast<float*>(s);
   g.out_a = acc;
   return hip_status(
-      traced(p, kStGatherForce, st, [&] { return launch_gather(lattice(p), kGatherForce, g, KickArgs{}, st); }));
+      traced(p, kStGatherForce, st, [&] {
+        return launch_gather(lattice(p), p->bins, bin_buffers(p, ws), kGatherForce, false, g, KickArgs{}, st);
+      }));
 }
 
 int cola_step(cola_plan p, int32_t i, const cola_particles* q, void* ws_, void* stream) {
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
   if (i < 0 || i >= p->cfg.n_steps) return COLA_ERR_RANGE;
-  hipStream_t st = (hipStream_t)stream;
-  float* ws = static_cast<float*>(ws_);
-  const StepRow& row = p->table[i];
-  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st));
-  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
-  KickArgs k{};
-  k.alpha = (float)row.alpha;
-  k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
-  k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
-  k.beta = (float)row.beta;
-  k.dd1 = plain ? 0.0f : (float)row.dd1;
-  k.dd2 = plain ? 0.0f : (float)row.dd2;
-  GatherArgs g = gather_args(p, ws);
-  g.s = q->s;
-  g.v = q->v;
-  g.s1 = q->s1;
-  g.s2 = q->s2;
-  return hip_status(
-      traced(p, kStGatherKickDrift, st, [&] { return launch_gather(lattice(p), kGatherKickDrift, g, k, st); }));
+  return step_impl(p, i, q, static_cast<float*>(ws_), (hipStream_t)stream, BinPlan{});
 }
 
 int cola_finish(cola_plan p, const cola_particles* q, float* x_out, float* v_out, void* ws_, void* stream) {
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
   if (!x_out || !v_out) return COLA_ERR_INVALID;
-  hipStream_t st = (hipStream_t)stream;
-  float* ws = static_cast<float*>(ws_);
-  const StepRow& row = p->table[p->cfg.n_steps];
-  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st));
-  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
-  KickArgs k{};
-  k.alpha = (float)row.alpha;
-  k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
-  k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
-  k.td1 = plain ? 0.0f : (float)row.g.td1;
-  k.td2 = plain ? 0.0f : (float)row.g.td2;
-  k.box = (float)p->cfg.box;
-  GatherArgs g = gather_args(p, ws);
-  g.s = q->s;
-  g.v = q->v;
-  g.s1 = q->s1;
-  g.s2 = q->s2;
-  g.out_a = x_out;
-  g.out_b = v_out;
-  return hip_status(traced(p, kStFinish, st, [&] { return launch_gather(lattice(p), kGatherFinish, g, k, st); }));
+  return finish_impl(p, q, x_out, v_out, static_cast<float*>(ws_), (hipStream_t)stream, BinPlan{});
 }
 
-int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out, float* v_out, void* ws,
+int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out, float* v_out, void* ws_,
              void* stream) {
-  COLA_TRY(cola_init_2lpt(p, w, q, ws, stream));
-  for (int i = 0; i < p->cfg.n_steps; ++i) COLA_TRY(cola_step(p, i, q, ws, stream));
-  return cola_finish(p, q, x_out, v_out, ws, stream);
+  COLA_TRY(cola_init_2lpt(p, w, q, ws_, stream));
+  if (!x_out || !v_out) return COLA_ERR_INVALID;
+  float* ws = static_cast<float*>(ws_);
+  hipStream_t st = (hipStream_t)stream;
+  const Lattice lat = lattice(p);
+  const Bins& b = p->bins;
+  const float mass = (float)std::pow((double)lat.ratio, 3);
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  // The state is kept sorted by tile in two workspace copies: every deposit writes
+  // the re-sorted copy, every gather bins the drifted particles for the next one.
+  int parity = 0;
+  BinBuffers bb = bin_buffers(p, ws, parity);
+  COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, q->s, bb, st); }));
+  SortedState src{q->s, q->v, q->s1, q->s2, nullptr};
+  int which = 0;
+  GatherArgs g = gather_args(p, ws);
+  for (int i = 0; i <= p->cfg.n_steps; ++i) {
+    const bool last = i == p->cfg.n_steps;
+    const StepRow& row = p->table[i];
+    bb = bin_buffers(p, ws, parity);
+    COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, !last, st); }));
+    COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
+    const SortedState dst = sorted_state(p, ws, which);
+    COLA_HIP(traced(p, kStDeposit, st, [&] { return launch_deposit_perm(lat, b, src, dst, bb, ws, mass, st); }));
+    COLA_HIP(traced(p, kStDepositMerge, st, [&] { return launch_deposit_merge(lat, b, bb, ws, st); }));
+    COLA_TRY(fft_force(p, row.a, ws, st));
+    KickArgs k{};
+    k.alpha = (float)row.alpha;
+    k.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
+    k.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
+    if (!last) {
+      k.beta = (float)row.beta;
+      k.dd1 = plain ? 0.0f : (float)row.dd1;
+      k.dd2 = plain ? 0.0f : (float)row.dd2;
+      COLA_HIP(traced(p, kStGatherKickDrift, st,
+                      [&] { return launch_gather_sorted(lat, b, dst, bb, kGatherKickDrift, g, k, st); }));
+      parity ^= 1;
+      src = dst;
+      which ^= 1;
+    } else {
+      k.td1 = plain ? 0.0f : (float)row.g.td1;
+      k.td2 = plain ? 0.0f : (float)row.g.td2;
+      k.box = (float)p->cfg.box;
+      g.s = q->s;
+      g.v = q->v;
+      g.out_a = x_out;
+      g.out_b = v_out;
+      COLA_HIP(traced(p, kStFinish, st, [&] { return launch_gather_sorted(lat, b, dst, bb, kGatherFinish, g, k, st); }));
+    }
+  }
+  return COLA_OK;
 }
 
 int cola_fft_r2c(cola_plan p, int32_t n, const float* in, float* out, void* stream) {
@@ -456,7 +575,7 @@ int cola_fft_r2c(cola_plan p, int32_t n, const float* in, float* out, void* stre
   const long h = n / 2;
   FieldPtrs f = fields({out});
   return hip_status(
-      traced(p, kStFft, st, [&] { return launch_col(n, -1, f, f, 1, n, h, (long)n * h, (int)h, tw, st); }));
+      traced(p, kStFft, st, [&] { return launch_col(n, -1, f, f, 1, n, h, (long)n * h, (int)h, tw, 0, st); }));
 }
 
 int cola_fft_c2r(cola_plan p, int32_t n, const float* in, float* out, void* stream) {
@@ -468,12 +587,20 @@ int cola_fft_c2r(cola_plan p, int32_t n, const float* in, float* out, void* stre
   const long h = n / 2;
   FieldPtrs fi = fields({const_cast<float*>(in)});
   FieldPtrs fo = fields({out});
-  COLA_HIP(traced(p, kStFft, st, [&] { return launch_col(n, 1, fi, fo, 1, n, h, (long)n * h, (int)h, tw, st); }));
+  COLA_HIP(
+      traced(p, kStFft, st, [&] { return launch_col(n, 1, fi, fo, 1, n, h, (long)n * h, (int)h, tw, 0, st); }));
   COLA_TRY(ypass(p, kStFft, n, 1, fo, 1, tw, st));
   EpiArgs e{};
   e.scale = (float)(1.0 / (double)cube(n));
   return hip_status(
       traced(p, kStFft, st, [&] { return launch_zinv(n, fo, fo, 1, (long)n * n, tw, kEpiStore, e, st); }));
+}
+
+int cola_plan_set_fft_tile(cola_plan p, int32_t pass, int32_t width) {
+  if (!p || pass < 0 || pass > 1) return COLA_ERR_INVALID;
+  if (!fft_width_supported(p->cfg.nm, width)) return COLA_ERR_UNSUPPORTED_SIZE;
+  p->fft_width[pass] = width;
+  return COLA_OK;
 }
 
 int cola_trace_enable(cola_plan p, int enable) {

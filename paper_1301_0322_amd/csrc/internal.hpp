@@ -57,13 +57,16 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
                                float scale, hipStream_t st);
 // Strided column pass (length n along inner_stride) over tiles of contiguous columns.
 // Tiles: outer index o in [0, n_outer) at outer_stride; columns [0, ncols) contiguous.
+// width: columns per tile (4, 8 or 16; 0 picks the default for n).
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, int n_outer,
-                      long outer_stride, long inner_stride, int ncols, const float2* tw,
+                      long outer_stride, long inner_stride, int ncols, const float2* tw, int width,
                       hipStream_t st);
 // x pass with the k-space multiplier: forward x transform of `in`, multiply, inverse
 // x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row.
 hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m,
-                       const float2* tw, hipStream_t st);
+                       const float2* tw, int width, hipStream_t st);
+// Whether `width` columns per tile is a valid strided-pass shape for length n.
+bool fft_width_supported(int n, int width);
 
 // Particle kernels.
 struct Lattice {
@@ -75,7 +78,36 @@ struct Lattice {
 };
 
 hipError_t launch_fill(float* p, long n, float value, hipStream_t st);
-hipError_t launch_deposit(Lattice lat, const float* s, float* rho, float mass, hipStream_t st);
+
+// Eulerian tiles of tx x ty x tz cells used to bin particles every step.
+struct Bins {
+  int tx, ty, tz;
+  int nbx, nby, nbz;
+  long nbins;
+  int halo;          // floats of halo faces stored per tile
+};
+struct BinBuffers {
+  int2* key_rank;    // [npart] (tile, rank within tile)
+  int* idx;          // [npart] particle indices grouped by tile
+  int* count;        // [count_len] particles per tile
+  int* count_next;   // [count_len] counts for the next step, filled by a binning gather
+  int* offset;       // [count_len] exclusive prefix sum, offset[nbins] = npart
+  float* halo;       // [nbins * halo] halo faces of each tile's deposit
+  long count_len;
+};
+Bins make_bins(int nm);
+size_t bin_workspace_bytes(long npart, const Bins& b);
+BinBuffers carve_bins(void* base, long npart, const Bins& b);
+
+hipError_t launch_bin_count(Lattice lat, Bins b, const float* s, BinBuffers bb, hipStream_t st);
+// clear_next also zeroes count_next for a binning gather later in the step.
+hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t st);
+hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
+// Tile deposit (cells written with plain stores, halo faces to the side buffer)
+// followed by the merge of the halo faces.  rho needs no clearing.
+hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
+                          hipStream_t st);
+hipError_t launch_deposit_merge(Lattice lat, Bins b, BinBuffers bb, float* rho, hipStream_t st);
 
 struct KickArgs {
   float alpha;                 // kick factor
@@ -101,7 +133,30 @@ struct GatherArgs {
   float* out_a;     // kGatherForce: acc; kGatherFinish: x
   float* out_b;     // kGatherFinish: v_phys
 };
-hipError_t launch_gather(Lattice lat, int mode, GatherArgs a, KickArgs k, hipStream_t st);
+// bin_next (kGatherKickDrift only): also count the drifted particles into
+// bb.count_next and write their (tile, rank) to bb.key_rank for the next step.
+hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
+                         hipStream_t st);
+
+// Particle state ordered by tile (slot j), with each particle's Lagrangian index.
+// As a deposit_perm source, lag == nullptr means slot = Lagrangian index (the
+// caller's arrays).
+struct SortedState {
+  float* s;
+  float* v;
+  float* s1;
+  float* s2;
+  int* lag;
+};
+// Deposit that also permutes src into dst in tile order (dst slot j holds the
+// particle src slot idx[j]).
+hipError_t launch_deposit_perm(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, float* rho,
+                               float mass, hipStream_t st);
+// Gather + kick on the sorted state.  kGatherKickDrift drifts in place and bins the
+// drifted particles (bb.count_next, bb.key_rank by slot); kGatherFinish writes the
+// final s, v, x and v_phys in Lagrangian order through a.s, a.v, a.out_a, a.out_b.
+hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a,
+                                KickArgs k, hipStream_t st);
 
 hipError_t launch_noise(uint64_t seed, float* w, long count, hipStream_t st);
 

@@ -41,8 +41,10 @@ constexpr int col_width() {
 
 // Threads per block of the strided passes: 512 for tiles of >= 8192 elements so
 // each lane holds at most 16 complex values.
-template <int N>
-constexpr int col_threads() { return N * col_width<N>() >= 8192 ? 512 : 256; }
+constexpr int col_threads_for(int n, int b) { return n * b >= 8192 ? 512 : 256; }
+// A column width is usable when it divides n/2 and the tile fits in 64 KB.
+template <int N, int B>
+constexpr bool col_ok() { return B >= 2 && B <= pow2_factor(N / 2) && N * B <= 8192; }
 
 __device__ __forceinline__ int pick_comp(int c, int nx, int ny, int nz) {
   return c == 0 ? nx : (c == 1 ? ny : nz);
@@ -64,26 +66,29 @@ template <int N>
 __global__ __launch_bounds__(kThreads) void k_zfwd(const float* in, float2* out, const float2* __restrict__ tw) {
   constexpr int M = N / 2;
   constexpr int BR = z_rows<N>();
-  __shared__ float2 tile[BR * M];
+  __shared__ __align__(16) float2 tile[BR * M];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
   const long row0 = (long)blockIdx.x * BR;
   const float4* src = reinterpret_cast<const float4*>(in + row0 * N);
-  for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) {
-    float4 v = src[idx];
-    tile[2 * idx] = make_float2(v.x, v.y);
-    tile[2 * idx + 1] = make_float2(v.z, v.w);
-  }
+  for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) reinterpret_cast<float4*>(tile)[idx] = src[idx];
   __syncthreads();
   fft_tile<M, BR, kThreads, 1, M, true, -1, 2>(tile, stw);
-  float2* dst = out + row0 * M;
-  for (int idx = threadIdx.x; idx < BR * M; idx += kThreads) {
-    const int b = idx / M, k = idx % M;
+  // X[k] and X[M-k] both come from the pair (Z[k], Z[M-k]).
+  constexpr int Q = M / 2 + 1;
+  for (int idx = threadIdx.x; idx < BR * Q; idx += kThreads) {
+    const int b = idx / Q, k = idx % Q;
+    float2* dst = out + (row0 + b) * M;
     const float2 zk = tile[b * M + k];
-    const float2 zm = c_conj(tile[b * M + ((M - k) % M)]);
-    const float2 a = c_scale(c_add(zk, zm), 0.5f);
-    const float2 d = c_scale(c_sub(zk, zm), 0.5f);
-    dst[idx] = c_add(a, mul_si<-1>(c_mul(stw[k], d)));
+    const float2 zm = tile[b * M + ((M - k) % M)];
+    const float2 a = c_scale(c_add(zk, c_conj(zm)), 0.5f);
+    const float2 d = c_scale(c_sub(zk, c_conj(zm)), 0.5f);
+    dst[k] = c_add(a, mul_si<-1>(c_mul(stw[k], d)));
+    if (k != 0 && k != M - k) {
+      const float2 a2 = c_scale(c_add(zm, c_conj(zk)), 0.5f);
+      const float2 d2 = c_scale(c_sub(zm, c_conj(zk)), 0.5f);
+      dst[M - k] = c_add(a2, mul_si<-1>(c_mul(stw[M - k], d2)));
+    }
   }
 }
 
@@ -92,29 +97,26 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(const float* in, float2* out,
 // Z'[k] = (X[k] + conj X[M-k]) + i W^-k (X[k] - conj X[M-k]) with X[M] = 0;
 // its unnormalised inverse length-M DFT is x[2m] + i x[2m+1].
 // ---------------------------------------------------------------------------------
+// Requires stw to be visible to the whole block on entry (callers synchronise
+// after loading it).
 template <int N, int BR>
 __device__ __forceinline__ void zinv_tile(float2* tile, const float2* stw, const float2* src) {
   constexpr int M = N / 2;
-  constexpr int PER = ceil_div(BR * M, kThreads);
-  for (int idx = threadIdx.x; idx < BR * M; idx += kThreads) tile[idx] = src[idx];
-  __syncthreads();
-  float2 z[PER];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * kThreads;
-    if ((BR * M) % kThreads == 0 || idx < BR * M) {
-      const int b = idx / M, k = idx % M;
-      const float2 xk = tile[idx];
-      const float2 xm = (k == 0) ? make_float2(0.f, 0.f) : c_conj(tile[b * M + (M - k)]);
-      const float2 w = c_conj(stw[k]);
-      z[i] = c_add(c_add(xk, xm), mul_si<1>(c_mul(w, c_sub(xk, xm))));
+  constexpr int Q = M / 2 + 1;   // work items per row: k = 0..M/2, each also producing M - k
+  // Each item loads X[k] and X[M-k] straight from memory and writes Z'[k], Z'[M-k].
+  for (int idx = threadIdx.x; idx < BR * Q; idx += kThreads) {
+    const int b = idx / Q, k = idx % Q;
+    const float2* row = src + b * M;
+    float2* out = tile + b * M;
+    const float2 xk = row[k];
+    if (k == 0) {
+      out[0] = c_add(xk, mul_si<1>(xk));                         // X[M] = 0
+    } else {
+      const float2 xm = row[M - k];
+      out[k] = c_add(c_add(xk, c_conj(xm)), mul_si<1>(c_mul(c_conj(stw[k]), c_sub(xk, c_conj(xm)))));
+      if (k != M - k)
+        out[M - k] = c_add(c_add(xm, c_conj(xk)), mul_si<1>(c_mul(c_conj(stw[M - k]), c_sub(xm, c_conj(xk)))));
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * kThreads;
-    if ((BR * M) % kThreads == 0 || idx < BR * M) tile[idx] = z[i];
   }
   __syncthreads();
   fft_tile<M, BR, kThreads, 1, M, true, 1, 2>(tile, stw);
@@ -125,17 +127,18 @@ __global__ __launch_bounds__(kThreads) void k_zinv(FieldPtrs in, FieldPtrs out, 
                                                    EpiArgs e) {
   constexpr int M = N / 2;
   constexpr int BR = z_rows<N>();
-  __shared__ float2 tile[BR * M];
+  __shared__ __align__(16) float2 tile[BR * M];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
+  __syncthreads();   // zinv_tile reads the twiddles before its first barrier
   const int f = blockIdx.y;
   const long row0 = (long)blockIdx.x * BR;
   zinv_tile<N, BR>(tile, stw, in.p[f] + row0 * M);
   float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(out.p[f]) + row0 * N);
   if constexpr (EPI == kEpiStore) {
     for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) {
-      const float2 a = tile[2 * idx], b = tile[2 * idx + 1];
-      dst[idx] = make_float4(a.x * e.scale, a.y * e.scale, b.x * e.scale, b.y * e.scale);
+      const float4 ab = reinterpret_cast<const float4*>(tile)[idx];
+      dst[idx] = make_float4(ab.x * e.scale, ab.y * e.scale, ab.z * e.scale, ab.w * e.scale);
     }
   } else {
     const long off = f * e.comp_stride + row0 * N;
@@ -143,8 +146,8 @@ __global__ __launch_bounds__(kThreads) void k_zinv(FieldPtrs in, FieldPtrs out, 
     float4* s = reinterpret_cast<float4*>(e.s + off);
     float4* v = reinterpret_cast<float4*>(e.v + off);
     for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) {
-      const float2 a = tile[2 * idx], b = tile[2 * idx + 1];
-      const float4 x2 = make_float4(a.x * e.scale, a.y * e.scale, b.x * e.scale, b.y * e.scale);
+      const float4 ab = reinterpret_cast<const float4*>(tile)[idx];
+      const float4 x2 = make_float4(ab.x * e.scale, ab.y * e.scale, ab.z * e.scale, ab.w * e.scale);
       const float4 x1 = s1[idx];
       dst[idx] = x2;
       s[idx] = make_float4(e.d1 * x1.x + e.d2 * x2.x, e.d1 * x1.y + e.d2 * x2.y,
@@ -162,9 +165,10 @@ __global__ __launch_bounds__(kThreads) void k_zinv_hess(FieldPtrs in, float* out
   constexpr int M = N / 2;
   constexpr int BR = zh_rows<N>();
   constexpr int PER = ceil_div(BR * M, kThreads);
-  __shared__ float2 tile[BR * M];
+  __shared__ __align__(16) float2 tile[BR * M];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
+  __syncthreads();   // zinv_tile reads the twiddles before its first barrier
   const long row0 = (long)blockIdx.x * BR;
   float2 dg[3][PER];
   float2 acc[PER];
@@ -209,9 +213,7 @@ template <int N, int B, int T>
 __device__ __forceinline__ void col_load(float2* tile, const float2* src, long inner_stride) {
   for (int idx = threadIdx.x; idx < N * B / 2; idx += T) {
     const int m = idx / (B / 2), q = idx % (B / 2);
-    const float4 v = *reinterpret_cast<const float4*>(src + m * inner_stride + 2 * q);
-    tile[m * B + 2 * q] = make_float2(v.x, v.y);
-    tile[m * B + 2 * q + 1] = make_float2(v.z, v.w);
+    reinterpret_cast<float4*>(tile)[idx] = *reinterpret_cast<const float4*>(src + m * inner_stride + 2 * q);
   }
 }
 
@@ -219,15 +221,14 @@ template <int N, int B, int T>
 __device__ __forceinline__ void col_store(const float2* tile, float2* dst, long inner_stride) {
   for (int idx = threadIdx.x; idx < N * B / 2; idx += T) {
     const int m = idx / (B / 2), q = idx % (B / 2);
-    const float2 a = tile[m * B + 2 * q], b = tile[m * B + 2 * q + 1];
-    *reinterpret_cast<float4*>(dst + m * inner_stride + 2 * q) = make_float4(a.x, a.y, b.x, b.y);
+    *reinterpret_cast<float4*>(dst + m * inner_stride + 2 * q) = reinterpret_cast<const float4*>(tile)[idx];
   }
 }
 
-template <int N, int B, int S, int T = col_threads<N>()>
+template <int N, int B, int S, int T = col_threads_for(N, B)>
 __global__ __launch_bounds__(T) void k_col(FieldPtrs in, FieldPtrs out, long outer_stride, long inner_stride,
                                            int ntiles_c, const float2* __restrict__ tw) {
-  __shared__ float2 tile[N * B];
+  __shared__ __align__(16) float2 tile[N * B];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
   const int f = blockIdx.y;
@@ -245,14 +246,14 @@ __global__ __launch_bounds__(T) void k_col(FieldPtrs in, FieldPtrs out, long out
 // at fixed y.  Mode numbers: nx from the row m, ny from y, nz = kz (< n/2).
 // Modes with nx or ny equal to n/2, and the k = 0 mode, get multiplier 0.
 // ---------------------------------------------------------------------------------
-template <int N, int B, int MODE, int T = col_threads<N>()>
+template <int N, int B, int MODE, int T = col_threads_for(N, B)>
 __global__ __launch_bounds__(T) void k_xmul(const float2* in, FieldPtrs out, int nout, MulArgs ma,
                                             const float2* __restrict__ tw) {
   constexpr int H = N / 2;
   constexpr int NT = H / B;
   constexpr int PER = ceil_div(N * B, T);
   constexpr bool FULL = (N * B) % T == 0;
-  __shared__ float2 tile[N * B];
+  __shared__ __align__(16) float2 tile[N * B];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
   const int tc = blockIdx.x % NT;
@@ -355,32 +356,88 @@ static hipError_t zinv_hess_t(FieldPtrs in, float* out, long nrows, const float2
   return hipGetLastError();
 }
 
-template <int N>
-static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                        long inner_stride, int ncols, const float2* tw, hipStream_t st) {
-  constexpr int B = col_width<N>();
-  if (ncols % B) return hipErrorInvalidValue;
-  const int ntc = ncols / B;
-  constexpr int T = col_threads<N>();
-  dim3 grid((unsigned)((long)n_outer * ntc), nf);
-  if (dir < 0)
-    hipLaunchKernelGGL((k_col<N, B, -1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw);
-  else
-    hipLaunchKernelGGL((k_col<N, B, 1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw);
-  return hipGetLastError();
+template <int N, int B>
+static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
+                         long inner_stride, int ncols, const float2* tw, hipStream_t st) {
+  if constexpr (col_ok<N, B>()) {
+    if (ncols % B) return hipErrorInvalidValue;
+    constexpr int T = col_threads_for(N, B);
+    const int ntc = ncols / B;
+    dim3 grid((unsigned)((long)n_outer * ntc), nf);
+    if (dir < 0)
+      hipLaunchKernelGGL((k_col<N, B, -1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw);
+    else
+      hipLaunchKernelGGL((k_col<N, B, 1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
 }
 
 template <int N>
+static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
+                        long inner_stride, int ncols, const float2* tw, int width, hipStream_t st) {
+  switch (width ? width : col_width<N>()) {
+    case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
+    case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
+    case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int B>
+static hipError_t xmul_tb(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
+                          hipStream_t st) {
+  if constexpr (col_ok<N, B>()) {
+    constexpr int T = col_threads_for(N, B);
+    dim3 grid(N * ((N / 2) / B));
+    if (mode == kMulGrad)
+      hipLaunchKernelGGL((k_xmul<N, B, kMulGrad>), grid, dim3(T), 0, st, in, out, nout, m, tw);
+    else
+      hipLaunchKernelGGL((k_xmul<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, out, nout, m, tw);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+// Default x-pass width: 8 columns where valid (the multi-output x pass holds the
+// forward spectrum in registers, so narrower tiles keep more blocks resident).
+template <int N>
+constexpr int xmul_width() { return col_ok<N, 8>() ? 8 : col_width<N>(); }
+
+template <int N>
 static hipError_t xmul_t(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
-                         hipStream_t st) {
-  constexpr int B = col_width<N>();
-  constexpr int T = col_threads<N>();
-  dim3 grid(N * ((N / 2) / B));
-  if (mode == kMulGrad)
-    hipLaunchKernelGGL((k_xmul<N, B, kMulGrad>), grid, dim3(T), 0, st, in, out, nout, m, tw);
-  else
-    hipLaunchKernelGGL((k_xmul<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, out, nout, m, tw);
-  return hipGetLastError();
+                         int width, hipStream_t st) {
+  switch (width ? width : xmul_width<N>()) {
+    case 4: return xmul_tb<N, 4>(mode, in, out, nout, m, tw, st);
+    case 8: return xmul_tb<N, 8>(mode, in, out, nout, m, tw, st);
+    case 16: return xmul_tb<N, 16>(mode, in, out, nout, m, tw, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+static bool width_ok(int w) {
+  switch (w) {
+    case 0: return true;
+    case 4: return col_ok<N, 4>();
+    case 8: return col_ok<N, 8>();
+    case 16: return col_ok<N, 16>();
+    default: return false;
+  }
+}
+
+bool fft_width_supported(int n, int width) {
+  switch (n) {
+#define COLA_CASE(N) \
+  case N:            \
+    return width_ok<N>(width);
+    COLA_FOR_EACH_SIZE(COLA_CASE)
+#undef COLA_CASE
+    default:
+      return false;
+  }
 }
 
 hipError_t launch_zfwd(int n, const float* in, float2* out, long nrows, const float2* tw, hipStream_t st) {
@@ -422,11 +479,11 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 }
 
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                      long inner_stride, int ncols, const float2* tw, hipStream_t st) {
+                      long inner_stride, int ncols, const float2* tw, int width, hipStream_t st) {
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
+    return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:
@@ -435,11 +492,11 @@ hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n
 }
 
 hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
-                       hipStream_t st) {
+                       int width, hipStream_t st) {
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return xmul_t<N>(mode, in, out, nout, m, tw, st);
+    return xmul_t<N>(mode, in, out, nout, m, tw, width, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:

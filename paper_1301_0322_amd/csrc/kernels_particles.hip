@@ -1,5 +1,5 @@
-// Per-particle kernels on gfx950: cloud-in-cell deposit, the fused CIC gather +
-// COLA kick + drift, Philox white noise and a fill kernel.
+// Per-particle kernels on gfx950: Eulerian binning, cloud-in-cell deposit, the
+// fused CIC gather + COLA kick + drift, Philox white noise and a fill kernel.
 //
 // Particles are in Lagrangian order p = (i np + j) np + k (k fastest) with SoA
 // components [3][np^3]; the Lagrangian position q = (i, j, k) L / np is implicit.
@@ -8,9 +8,11 @@
 // evaluated as an exact integer plus a small FP32 remainder so the CIC weights keep
 // full FP32 precision on large meshes.
 //
-// Blocks are remapped so that each of the 8 XCDs (which receive blocks round-robin)
-// works on one contiguous, spatially coherent slab of particles and shares its L2.
+// Tile blocks are remapped so that each of the 8 XCDs (which receive blocks
+// round-robin) works on one contiguous slab of tiles and shares its L2 with the
+// neighbouring tiles whose halo rows it reads.
 #include "internal.hpp"
+
 
 namespace cola {
 
@@ -22,31 +24,9 @@ __device__ __forceinline__ long xcd_block(long nblocks_padded) {
   return (b % kXcds) * (nblocks_padded / kXcds) + b / kXcds;
 }
 
-struct Stencil {
-  int c0[3], c1[3];
-  float w1[3];
-};
-
 __device__ __forceinline__ int wrap(int c, int n) {
   c %= n;
   return c < 0 ? c + n : c;
-}
-
-__device__ __forceinline__ Stencil make_stencil(const Lattice& lat, long p, float sx, float sy, float sz) {
-  const long np2 = (long)lat.np * lat.np;
-  const int li[3] = {(int)(p / np2), (int)((p / lat.np) % lat.np), (int)(p % lat.np)};
-  const float sd[3] = {sx, sy, sz};
-  Stencil st;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float t = sd[d] * lat.inv_dx - 0.5f;
-    const float ft = floorf(t);
-    st.w1[d] = t - ft;
-    const int c = wrap(lat.ratio * li[d] + (int)ft, lat.nm);
-    st.c0[d] = c;
-    st.c1[d] = (c + 1 == lat.nm) ? 0 : c + 1;
-  }
-  return st;
 }
 
 // ---------------------------------------------------------------------------------
@@ -56,88 +36,514 @@ __global__ __launch_bounds__(kPartThreads) void k_fill(float4* p, long n4, float
 }
 
 // ---------------------------------------------------------------------------------
-// Deposit: rho[c] += mass * prod_d w_d for the 8 cells of each particle.
+// Eulerian binning.  The mesh is cut into tiles of tx x ty x tz cells; every step
+// the particles are binned by the tile of their base cell (the lower corner of
+// their CIC stencil), so that deposit and gather run tile by tile through LDS:
+//   bin_count   wavefront-aggregated atomics give each particle its rank in its
+//               tile (lanes sharing a tile take one atomic between them);
+//   bin_scan    exclusive prefix sum of the tile counts;
+//   bin_scatter idx[offset[tile] + rank] = p;
+//   deposit     per tile: LDS atomics over the tile plus its +1 halo, then plain
+//               stores of the tile's cells and of its halo faces to a side buffer;
+//   merge       per tile: add the lower neighbours' halo faces to the tile's low
+//               faces (every cell has one writer: no global float atomics);
+//   gather      per tile: the three force meshes over tile + halo read once into
+//               LDS, then every particle of the tile reads its 8 corners there.
 // ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(kPartThreads) void k_deposit(Lattice lat, const float* __restrict__ s,
-                                                          float* __restrict__ rho, float mass, long nbp) {
-  const long p = xcd_block(nbp) * kPartThreads + threadIdx.x;
-  if (p >= lat.npart) return;
-  const float sx = s[p], sy = s[lat.npart + p], sz = s[2 * lat.npart + p];
-  const Stencil st = make_stencil(lat, p, sx, sy, sz);
-  const long nm = lat.nm;
-  const float wx[2] = {1.f - st.w1[0], st.w1[0]};
-  const float wy[2] = {1.f - st.w1[1], st.w1[1]};
-  const float wz[2] = {1.f - st.w1[2], st.w1[2]};
-  const int cx[2] = {st.c0[0], st.c1[0]};
-  const int cy[2] = {st.c0[1], st.c1[1]};
-  const int cz[2] = {st.c0[2], st.c1[2]};
+constexpr int kTX = 8, kTY = 8;   // tile cells along x and y; tz (8, 16 or 32) is a template parameter
+
+template <int TZ>
+struct TileDims {
+  static constexpr int EY = kTY + 1, EZ = TZ + 1;           // extents with the +1 halo
+  static constexpr int EXT = (kTX + 1) * EY * EZ;
+  static constexpr int CORE = kTX * kTY * TZ;
+  static constexpr int FX = EY * EZ;                         // face x = tx: y <= ty, z <= tz
+  static constexpr int FY = kTX * EZ;                        // face y = ty: x < tx, z <= tz
+  static constexpr int FZ = kTX * kTY;                       // face z = tz: x < tx, y < ty
+  static constexpr int HALO = FX + FY + FZ;
+};
+
+// Base cell (wrapped) and CIC fraction along one axis.
+__device__ __forceinline__ int base_cell(int lag, int ratio, float s, float inv_dx, int nm, float& frac) {
+  const float t = fmaf(s, inv_dx, -0.5f);
+  const float ft = floorf(t);
+  frac = t - ft;
+  const int c = ratio * lag + (int)ft;
+  return ((unsigned)c < (unsigned)nm) ? c : wrap(c, nm);
+}
+
+__device__ __forceinline__ void lag_index(const Lattice& lat, unsigned p, int li[3]) {
+  const unsigned n = (unsigned)lat.np;
+  const unsigned q = p / n;
+  li[2] = (int)(p - q * n);
+  li[1] = (int)(q % n);
+  li[0] = (int)(q / n);
+}
+
+struct Stencil {
+  int c[3];     // wrapped base cell
+  float f[3];   // fraction towards cell + 1
+};
+
+__device__ __forceinline__ Stencil stencil_of(const Lattice& lat, unsigned p, const float sv[3]) {
+  int li[3];
+  lag_index(lat, p, li);
+  Stencil st;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int d = 0; d < 3; ++d) st.c[d] = base_cell(li[d], lat.ratio, sv[d], lat.inv_dx, lat.nm, st.f[d]);
+  return st;
+}
+
+template <int TZ>
+__device__ __forceinline__ int bin_of(const Bins& b, const int c[3]) {
+  return ((c[0] / kTX) * b.nby + c[1] / kTY) * b.nbz + c[2] / TZ;
+}
+
+// Rank of each active lane among the lanes of its wave with the same bin, plus one
+// atomic per distinct bin that reserves the ranks.  Called by every lane of the wave.
+__device__ __forceinline__ int wave_rank(bool active, int bin, int* __restrict__ count) {
+  const int lane = __lane_id();
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long pending = __ballot(active);
+  int rank = 0;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int lb = __shfl(bin, leader);
+    const unsigned long long m = __ballot(active && bin == lb);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(count + lb, __popcll(m));
+    base = __shfl(base, leader);
+    if (active && bin == lb) rank = base + __popcll(m & lt);
+    pending &= ~m;
+  }
+  return rank;
+}
+
+template <int TZ>
+__global__ __launch_bounds__(kPartThreads) void k_bin_count(Lattice lat, Bins bins, const float* __restrict__ s,
+                                                            int2* __restrict__ key_rank, int* __restrict__ count) {
+  const unsigned p = blockIdx.x * kPartThreads + threadIdx.x;
+  const bool ok = p < (unsigned)lat.npart;
+  int bin = 0;
+  if (ok) {
+    const float sv[3] = {s[p], s[lat.npart + p], s[2 * lat.npart + p]};
+    const Stencil st = stencil_of(lat, p, sv);
+    bin = bin_of<TZ>(bins, st.c);
+  }
+  const int rank = wave_rank(ok, bin, count);
+  if (ok) key_rank[p] = make_int2(bin, rank);
+}
+
+// Exclusive scan of count[0..n) into offset[0..n] (offset[n] = total) by one block
+// of 16 waves, each owning a contiguous segment; also clears count_next[0..n_pad).
+__global__ __launch_bounds__(1024) void k_bin_scan(const int* __restrict__ count, int* __restrict__ offset, int n,
+                                                   int* __restrict__ count_next, int n_pad) {
+  __shared__ int wsum[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int seg = (n + 15) / 16;
+  const int lo = wave * seg, hi = min(n, lo + seg);
+  int sum = 0;
+  for (int i = lo + lane; i < hi; i += 64) sum += count[i];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const long row = ((long)cx[a] * nm + cy[b]) * nm;
-      const float wab = mass * wx[a] * wy[b];
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+  if (lane == 0) wsum[wave] = sum;
+  __syncthreads();
+  int carry = 0;
+  for (int w = 0; w < wave; ++w) carry += wsum[w];
+  for (int c = lo; c < hi; c += 64) {
+    const int i = c + lane;
+    const int v = i < hi ? count[i] : 0;
+    int inc = v;
 #pragma unroll
-      for (int c = 0; c < 2; ++c) unsafeAtomicAdd(rho + row + cz[c], wab * wz[c]);
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
     }
+    if (i < hi) offset[i] = carry + inc - v;
+    carry += __shfl(inc, 63);
+  }
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int w = 0; w < 16; ++w) tot += wsum[w];
+    offset[n] = tot;
+  }
+  if (count_next)
+    for (int i = threadIdx.x; i < n_pad; i += 1024) count_next[i] = 0;
+}
+
+__global__ __launch_bounds__(kPartThreads) void k_bin_scatter(long npart, const int2* __restrict__ key_rank,
+                                                              const int* __restrict__ offset, int* __restrict__ idx) {
+  const long p = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  if (p >= npart) return;
+  const int2 kr = key_rank[p];
+  idx[offset[kr.x] + kr.y] = (int)p;
+}
+
+struct TileGeom {
+  int bin;
+  int lo[3];
+};
+
+template <int TZ>
+__device__ __forceinline__ bool tile_geom(const Bins& b, TileGeom& g) {
+  const long nb = (b.nbins + kXcds - 1) / kXcds * kXcds;
+  g.bin = (int)xcd_block(nb);
+  if (g.bin >= b.nbins) return false;
+  const int bz = g.bin % b.nbz;
+  const int r = g.bin / b.nbz;
+  g.lo[0] = (r / b.nby) * kTX;
+  g.lo[1] = (r % b.nby) * kTY;
+  g.lo[2] = bz * TZ;
+  return true;
+}
+
+// Tile-local stencil of particle p; false if its base cell is not in this tile
+// (never the case: binning used the same arithmetic).
+template <int TZ>
+__device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom& g, const float* s, unsigned p,
+                                              float sv[3], int lc[3], float fr[3]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) sv[d] = s[d * lat.npart + p];
+  const Stencil st = stencil_of(lat, p, sv);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lc[d] = st.c[d] - g.lo[d];
+    fr[d] = st.f[d];
+  }
+  return (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
+}
+
+template <int TZ>
+__global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
+                                                                const int* __restrict__ idx,
+                                                                const int* __restrict__ offset, float* __restrict__ rho,
+                                                                float* __restrict__ halo, float mass) {
+  using D = TileDims<TZ>;
+  __shared__ float tile[D::EXT];
+  TileGeom g;
+  if (!tile_geom<TZ>(bins, g)) return;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0.f;
+  __syncthreads();
+  const int beg = offset[g.bin], end = offset[g.bin + 1];
+  // two particles per lane per iteration so their dependent loads overlap
+  for (int i = beg + threadIdx.x; i < end; i += 2 * kPartThreads) {
+    float sv[2][3], fr[2][3];
+    int lc[2][3];
+    bool ok[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int j = i + u * kPartThreads;
+      ok[u] = local_stencil<TZ>(lat, g, s, (unsigned)idx[j < end ? j : i], sv[u], lc[u], fr[u]) && j < end;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (!ok[u]) continue;
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const float wab = mass * (a ? fr[u][0] : 1.f - fr[u][0]) * (b ? fr[u][1] : 1.f - fr[u][1]);
+          float* row = tile + ((lc[u][0] + a) * D::EY + lc[u][1] + b) * D::EZ + lc[u][2];
+          atomicAdd(row, wab * (1.f - fr[u][2]));
+          atomicAdd(row + 1, wab * fr[u][2]);
+        }
+    }
+  }
+  __syncthreads();
+  const long nm = lat.nm;
+  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
+    const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
+    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile[(x * D::EY + y) * D::EZ + z];
+  }
+  float* h = halo + (long)g.bin * D::HALO;
+  for (int i = threadIdx.x; i < D::FX; i += kPartThreads) h[i] = tile[kTX * D::EY * D::EZ + i];
+  for (int i = threadIdx.x; i < D::FY; i += kPartThreads) {
+    const int x = i / D::EZ, z = i % D::EZ;
+    h[D::FX + i] = tile[(x * D::EY + kTY) * D::EZ + z];
+  }
+  for (int i = threadIdx.x; i < D::FZ; i += kPartThreads) {
+    const int x = i / kTY, y = i % kTY;
+    h[D::FX + D::FY + i] = tile[(x * D::EY + y) * D::EZ + TZ];
+  }
+}
+
+// Adds the lower neighbours' halo faces onto the tile's cells with a zero local
+// coordinate.
+template <int TZ>
+__global__ __launch_bounds__(kPartThreads) void k_deposit_merge(Lattice lat, Bins bins, float* __restrict__ rho,
+                                                                const float* __restrict__ halo) {
+  using D = TileDims<TZ>;
+  TileGeom g;
+  if (!tile_geom<TZ>(bins, g)) return;
+  const int bx = g.lo[0] / kTX, by = g.lo[1] / kTY, bz = g.lo[2] / TZ;
+  const int mx = (bx + bins.nbx - 1) % bins.nbx, my = (by + bins.nby - 1) % bins.nby,
+            mz = (bz + bins.nbz - 1) % bins.nbz;
+  auto face = [&](int X, int Y, int Z) { return halo + (((long)X * bins.nby + Y) * bins.nbz + Z) * D::HALO; };
+  const float* hx = face(mx, by, bz);
+  const float* hy = face(bx, my, bz);
+  const float* hz = face(bx, by, mz);
+  const float* hxy = face(mx, my, bz);
+  const float* hxz = face(mx, by, mz);
+  const float* hyz = face(bx, my, mz);
+  const float* hxyz = face(mx, my, mz);
+  constexpr int NA = kTY * TZ, NB = (kTX - 1) * TZ, NC = (kTX - 1) * (kTY - 1);
+  const long nm = lat.nm;
+  for (int i = threadIdx.x; i < NA + NB + NC; i += kPartThreads) {
+    int x, y, z;
+    if (i < NA) {
+      x = 0; y = i / TZ; z = i % TZ;
+    } else if (i < NA + NB) {
+      const int j = i - NA;
+      x = 1 + j / TZ; y = 0; z = j % TZ;
+    } else {
+      const int j = i - NA - NB;
+      x = 1 + j / (kTY - 1); y = 1 + j % (kTY - 1); z = 0;
+    }
+    float acc = 0.f;
+    if (x == 0) acc += hx[y * D::EZ + z];
+    if (y == 0) acc += hy[D::FX + x * D::EZ + z];
+    if (z == 0) acc += hz[D::FX + D::FY + x * kTY + y];
+    if (x == 0 && y == 0) acc += hxy[kTY * D::EZ + z];
+    if (x == 0 && z == 0) acc += hxz[y * D::EZ + TZ];
+    if (y == 0 && z == 0) acc += hyz[D::FX + x * D::EZ + TZ];
+    if (x == 0 && y == 0 && z == 0) acc += hxyz[kTY * D::EZ + TZ];
+    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] += acc;
+  }
 }
 
 // ---------------------------------------------------------------------------------
-// Gather + kick (+ drift | + finish).
+// Gather + kick (+ drift | + finish), tile by tile.  With BIN_NEXT the drifted
+// particles are also counted into next step's tiles (count_next, key_rank_next).
 // ---------------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(kPartThreads) void k_gather(Lattice lat, GatherArgs g, KickArgs k, long nbp) {
-  const long p = xcd_block(nbp) * kPartThreads + threadIdx.x;
-  if (p >= lat.npart) return;
+template <int TZ, int MODE, bool BIN_NEXT>
+__global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins bins, const int* __restrict__ idx,
+                                                               const int* __restrict__ offset, GatherArgs g,
+                                                               KickArgs k, int2* __restrict__ key_rank_next,
+                                                               int* __restrict__ count_next) {
+  using D = TileDims<TZ>;
+  __shared__ float tile[3 * D::EXT];
+  TileGeom t;
+  if (!tile_geom<TZ>(bins, t)) return;
+  const int nm = lat.nm;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) {
+    const int z = i % D::EZ, r = i / D::EZ;
+    const int y = r % D::EY, x = r / D::EY;
+    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
+    gx -= (gx >= nm) ? nm : 0;
+    gy -= (gy >= nm) ? nm : 0;
+    gz -= (gz >= nm) ? nm : 0;
+    const long gi = ((long)gx * nm + gy) * nm + gz;
+    tile[i] = g.g0[gi];
+    tile[D::EXT + i] = g.g1[gi];
+    tile[2 * D::EXT + i] = g.g2[gi];
+  }
+  __syncthreads();
   const long n = lat.npart;
-  float s3[3] = {g.s[p], g.s[n + p], g.s[2 * n + p]};
-  const Stencil st = make_stencil(lat, p, s3[0], s3[1], s3[2]);
-  const long nm = lat.nm;
-  const float wx[2] = {1.f - st.w1[0], st.w1[0]};
-  const float wy[2] = {1.f - st.w1[1], st.w1[1]};
-  const float wz[2] = {1.f - st.w1[2], st.w1[2]};
-  const int cx[2] = {st.c0[0], st.c1[0]};
-  const int cy[2] = {st.c0[1], st.c1[1]};
-  const int cz[2] = {st.c0[2], st.c1[2]};
-  float f[3] = {0.f, 0.f, 0.f};
+  const int beg = offset[t.bin], end = offset[t.bin + 1];
+  for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
+    const int i = base + threadIdx.x;
+    const unsigned p = (unsigned)idx[i < end ? i : base];
+    float sv[3], fr[3];
+    int lc[3];
+    const bool act = local_stencil<TZ>(lat, t, g.s, p, sv, lc, fr) && i < end;
+    float f[3] = {0.f, 0.f, 0.f};
+    if (act) {
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const long row = ((long)cx[a] * nm + cy[b]) * nm;
-      const float wab = wx[a] * wy[b];
+        for (int b = 0; b < 2; ++b) {
+          const float wab = (a ? fr[0] : 1.f - fr[0]) * (b ? fr[1] : 1.f - fr[1]);
+          const float w0 = wab * (1.f - fr[2]), w1 = wab * fr[2];
+          const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
 #pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const long idx = row + cz[c];
-        const float w = wab * wz[c];
-        f[0] += w * g.g0[idx];
-        f[1] += w * g.g1[idx];
-        f[2] += w * g.g2[idx];
+          for (int d = 0; d < 3; ++d) f[d] += w0 * tile[d * D::EXT + o] + w1 * tile[d * D::EXT + o + 1];
+        }
+    }
+    float snew[3] = {sv[0], sv[1], sv[2]};
+    if (act) {
+      if constexpr (MODE == kGatherForce) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) g.out_a[d * n + p] = f[d];
+      } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const float a1 = g.s1[d * n + p];
+          const float a2 = g.s2[d * n + p];
+          float v = g.v[d * n + p];
+          v += k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
+          g.v[d * n + p] = v;
+          if constexpr (MODE == kGatherKickDrift) {
+            snew[d] = sv[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
+            g.s[d * n + p] = snew[d];
+          } else {
+            g.out_b[d * n + p] = v + k.td1 * a1 + k.td2 * a2;
+            int li[3];
+            lag_index(lat, p, li);
+            float x = (float)li[d] * (k.box / (float)lat.np) + sv[d];
+            x = x - k.box * floorf(x / k.box);
+            if (x >= k.box) x -= k.box;
+            g.out_a[d * n + p] = x;
+          }
+        }
       }
     }
-  if constexpr (MODE == kGatherForce) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) g.out_a[d * n + p] = f[d];
-    return;
-  } else {
+    if constexpr (BIN_NEXT) {
+      int bin = 0;
+      if (act) bin = bin_of<TZ>(bins, stencil_of(lat, p, snew).c);
+      const int rank = wave_rank(act, bin, count_next);
+      if (act) key_rank_next[p] = make_int2(bin, rank);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Tile-sorted particle state (used by whole runs).  The state lives in workspace
+// buffers ordered by the tile of the particles' current base cell, with each
+// particle's Lagrangian index stored beside it:
+//   deposit_perm  per destination tile: reads the previous buffer through idx (runs
+//                 of consecutive source slots), writes the sorted copy and deposits;
+//   gather_sorted per tile: coalesced gather + kick + drift on the sorted copy, then
+//                 counts the drifted particles into next step's tiles.
+// ---------------------------------------------------------------------------------
+template <int TZ>
+__global__ __launch_bounds__(kPartThreads) void k_deposit_perm(Lattice lat, Bins bins, SortedState src,
+                                                               SortedState dst, const int* __restrict__ idx,
+                                                               const int* __restrict__ offset, float* __restrict__ rho,
+                                                               float* __restrict__ halo, float mass) {
+  using D = TileDims<TZ>;
+  __shared__ float tile[D::EXT];
+  TileGeom g;
+  if (!tile_geom<TZ>(bins, g)) return;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0.f;
+  __syncthreads();
+  const long n = lat.npart;
+  const int beg = offset[g.bin], end = offset[g.bin + 1];
+  for (int j = beg + threadIdx.x; j < end; j += kPartThreads) {
+    const int from = idx[j];
+    const unsigned lag = src.lag ? (unsigned)src.lag[from] : (unsigned)from;
+    float sv[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      const float a1 = g.s1[d * n + p];
-      const float a2 = g.s2[d * n + p];
-      float v = g.v[d * n + p];
-      v += k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
-      if constexpr (MODE == kGatherKickDrift) {
-        g.v[d * n + p] = v;
-        g.s[d * n + p] = s3[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
-      } else {
-        g.v[d * n + p] = v;
-        g.out_b[d * n + p] = v + k.td1 * a1 + k.td2 * a2;
-        const long li = (d == 0) ? p / ((long)lat.np * lat.np) : (d == 1) ? (p / lat.np) % lat.np : p % lat.np;
-        float x = (float)li * (k.box / (float)lat.np) + s3[d];
-        x = x - k.box * floorf(x / k.box);
-        if (x >= k.box) x -= k.box;
-        g.out_a[d * n + p] = x;
+      sv[d] = src.s[d * n + from];
+      dst.s[d * n + j] = sv[d];
+      dst.v[d * n + j] = src.v[d * n + from];
+      dst.s1[d * n + j] = src.s1[d * n + from];
+      dst.s2[d * n + j] = src.s2[d * n + from];
+    }
+    dst.lag[j] = (int)lag;
+    const Stencil st = stencil_of(lat, lag, sv);
+    const int lc[3] = {st.c[0] - g.lo[0], st.c[1] - g.lo[1], st.c[2] - g.lo[2]};
+    if ((unsigned)lc[0] >= (unsigned)kTX || (unsigned)lc[1] >= (unsigned)kTY || (unsigned)lc[2] >= (unsigned)TZ)
+      continue;   // cannot happen: binning used the same arithmetic
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const float wab = mass * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
+        float* row = tile + ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
+        atomicAdd(row, wab * (1.f - st.f[2]));
+        atomicAdd(row + 1, wab * st.f[2]);
       }
+  }
+  __syncthreads();
+  const long nm = lat.nm;
+  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
+    const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
+    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile[(x * D::EY + y) * D::EZ + z];
+  }
+  float* h = halo + (long)g.bin * D::HALO;
+  for (int i = threadIdx.x; i < D::FX; i += kPartThreads) h[i] = tile[kTX * D::EY * D::EZ + i];
+  for (int i = threadIdx.x; i < D::FY; i += kPartThreads) {
+    const int x = i / D::EZ, z = i % D::EZ;
+    h[D::FX + i] = tile[(x * D::EY + kTY) * D::EZ + z];
+  }
+  for (int i = threadIdx.x; i < D::FZ; i += kPartThreads) {
+    const int x = i / kTY, y = i % kTY;
+    h[D::FX + D::FY + i] = tile[(x * D::EY + y) * D::EZ + TZ];
+  }
+}
+
+template <int TZ, int MODE>
+__global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bins bins, SortedState st_,
+                                                                const int* __restrict__ offset, GatherArgs g,
+                                                                KickArgs k, int2* __restrict__ key_rank_next,
+                                                                int* __restrict__ count_next) {
+  using D = TileDims<TZ>;
+  __shared__ float tile[3 * D::EXT];
+  TileGeom t;
+  if (!tile_geom<TZ>(bins, t)) return;
+  const int nm = lat.nm;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) {
+    const int z = i % D::EZ, r = i / D::EZ;
+    const int y = r % D::EY, x = r / D::EY;
+    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
+    gx -= (gx >= nm) ? nm : 0;
+    gy -= (gy >= nm) ? nm : 0;
+    gz -= (gz >= nm) ? nm : 0;
+    const long gi = ((long)gx * nm + gy) * nm + gz;
+    tile[i] = g.g0[gi];
+    tile[D::EXT + i] = g.g1[gi];
+    tile[2 * D::EXT + i] = g.g2[gi];
+  }
+  __syncthreads();
+  const long n = lat.npart;
+  const int beg = offset[t.bin], end = offset[t.bin + 1];
+  for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
+    const int j = base + threadIdx.x;
+    const bool in = j < end;
+    const int jj = in ? j : base;
+    const unsigned lag = (unsigned)st_.lag[jj];
+    float sv[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) sv[d] = st_.s[d * n + jj];
+    const Stencil sc = stencil_of(lat, lag, sv);
+    const int lc[3] = {sc.c[0] - t.lo[0], sc.c[1] - t.lo[1], sc.c[2] - t.lo[2]};
+    const bool act =
+        in && (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
+    float f[3] = {0.f, 0.f, 0.f};
+    if (act) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const float wab = (a ? sc.f[0] : 1.f - sc.f[0]) * (b ? sc.f[1] : 1.f - sc.f[1]);
+          const float w0 = wab * (1.f - sc.f[2]), w1 = wab * sc.f[2];
+          const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) f[d] += w0 * tile[d * D::EXT + o] + w1 * tile[d * D::EXT + o + 1];
+        }
+    }
+    float snew[3] = {sv[0], sv[1], sv[2]};
+    if (act) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const float a1 = st_.s1[d * n + j];
+        const float a2 = st_.s2[d * n + j];
+        float v = st_.v[d * n + j];
+        v += k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
+        if constexpr (MODE == kGatherKickDrift) {
+          snew[d] = sv[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
+          st_.v[d * n + j] = v;
+          st_.s[d * n + j] = snew[d];
+        } else {
+          // finish: state back to Lagrangian order, positions and full velocities out
+          g.v[d * n + lag] = v;
+          g.s[d * n + lag] = sv[d];
+          g.out_b[d * n + lag] = v + k.td1 * a1 + k.td2 * a2;
+          int li[3];
+          lag_index(lat, lag, li);
+          float x = (float)li[d] * (k.box / (float)lat.np) + sv[d];
+          x = x - k.box * floorf(x / k.box);
+          if (x >= k.box) x -= k.box;
+          g.out_a[d * n + lag] = x;
+        }
+      }
+    }
+    if constexpr (MODE == kGatherKickDrift) {
+      int bin = 0;
+      if (act) bin = bin_of<TZ>(bins, stencil_of(lat, lag, snew).c);
+      const int rank = wave_rank(act, bin, count_next);
+      if (act) key_rank_next[j] = make_int2(bin, rank);
     }
   }
 }
@@ -189,9 +595,44 @@ __global__ __launch_bounds__(kPartThreads) void k_noise(uint64_t seed, float* __
 }
 
 // ---------------------------------------------------------------------------------
-static long padded_blocks(long npart) {
-  long nb = (npart + kPartThreads - 1) / kPartThreads;
-  return (nb + kXcds - 1) / kXcds * kXcds;
+Bins make_bins(int nm) {
+  Bins b;
+  b.tx = kTX;
+  b.ty = kTY;
+  b.tz = 8;
+  while (b.tz < 32 && nm % (2 * b.tz) == 0) b.tz *= 2;
+  b.nbx = nm / b.tx;
+  b.nby = nm / b.ty;
+  b.nbz = nm / b.tz;
+  b.nbins = (long)b.nbx * b.nby * b.nbz;
+  b.halo = (b.ty + 1) * (b.tz + 1) + b.tx * (b.tz + 1) + b.tx * b.ty;
+  return b;
+}
+
+static size_t count_len(const Bins& b) { return (size_t)((b.nbins + 4) / 4 * 4); }
+
+size_t bin_workspace_bytes(long npart, const Bins& b) {
+  return npart * sizeof(int2) + npart * sizeof(int) + 3 * count_len(b) * sizeof(int) +
+         (size_t)b.nbins * b.halo * sizeof(float);
+}
+
+BinBuffers carve_bins(void* base, long npart, const Bins& b) {
+  char* c = static_cast<char*>(base);
+  const size_t cnt = count_len(b);
+  BinBuffers bb;
+  bb.key_rank = reinterpret_cast<int2*>(c);
+  c += npart * sizeof(int2);
+  bb.idx = reinterpret_cast<int*>(c);
+  c += npart * sizeof(int);
+  bb.count = reinterpret_cast<int*>(c);
+  c += cnt * sizeof(int);
+  bb.count_next = reinterpret_cast<int*>(c);
+  c += cnt * sizeof(int);
+  bb.offset = reinterpret_cast<int*>(c);
+  c += cnt * sizeof(int);
+  bb.halo = reinterpret_cast<float*>(c);
+  bb.count_len = (long)cnt;
+  return bb;
 }
 
 hipError_t launch_fill(float* p, long n, float value, hipStream_t st) {
@@ -202,27 +643,98 @@ hipError_t launch_fill(float* p, long n, float value, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_deposit(Lattice lat, const float* s, float* rho, float mass, hipStream_t st) {
-  const long nb = padded_blocks(lat.npart);
-  hipLaunchKernelGGL(k_deposit, dim3((unsigned)nb), dim3(kPartThreads), 0, st, lat, s, rho, mass, nb);
+static unsigned part_blocks(long npart) { return (unsigned)((npart + kPartThreads - 1) / kPartThreads); }
+static unsigned tile_blocks(const Bins& b) { return (unsigned)((b.nbins + kXcds - 1) / kXcds * kXcds); }
+
+#define COLA_TZ_DISPATCH(tz, CALL) \
+  switch (tz) {                    \
+    case 8: { constexpr int TZ = 8; CALL; break; }   \
+    case 16: { constexpr int TZ = 16; CALL; break; } \
+    case 32: { constexpr int TZ = 32; CALL; break; } \
+    default: return hipErrorInvalidValue;            \
+  }
+
+hipError_t launch_bin_count(Lattice lat, Bins b, const float* s, BinBuffers bb, hipStream_t st) {
+  hipError_t e = launch_fill(reinterpret_cast<float*>(bb.count), bb.count_len, 0.0f, st);
+  if (e != hipSuccess) return e;
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_bin_count<TZ>, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st,
+                                            lat, b, s, bb.key_rank, bb.count));
   return hipGetLastError();
 }
 
-hipError_t launch_gather(Lattice lat, int mode, GatherArgs a, KickArgs k, hipStream_t st) {
-  const long nb = padded_blocks(lat.npart);
-  switch (mode) {
-    case kGatherForce:
-      hipLaunchKernelGGL(k_gather<kGatherForce>, dim3((unsigned)nb), dim3(kPartThreads), 0, st, lat, a, k, nb);
-      break;
-    case kGatherKickDrift:
-      hipLaunchKernelGGL(k_gather<kGatherKickDrift>, dim3((unsigned)nb), dim3(kPartThreads), 0, st, lat, a, k, nb);
-      break;
-    case kGatherFinish:
-      hipLaunchKernelGGL(k_gather<kGatherFinish>, dim3((unsigned)nb), dim3(kPartThreads), 0, st, lat, a, k, nb);
-      break;
-    default:
-      return hipErrorInvalidValue;
-  }
+hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bb.count, bb.offset, (int)b.nbins,
+                     clear_next ? bb.count_next : nullptr, (int)bb.count_len);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
+  hipLaunchKernelGGL(k_bin_scatter, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat.npart, bb.key_rank,
+                     bb.offset, bb.idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
+                          hipStream_t st) {
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_tiles<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
+                                            lat, b, s, bb.idx, bb.offset, rho, bb.halo, mass));
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit_merge(Lattice lat, Bins b, BinBuffers bb, float* rho, hipStream_t st) {
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_merge<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
+                                            lat, b, rho, bb.halo));
+  return hipGetLastError();
+}
+
+template <int TZ>
+static void gather_tz(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
+                      hipStream_t st) {
+  const dim3 grid(tile_blocks(b)), block(kPartThreads);
+  if (mode == kGatherForce)
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherForce, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a, k,
+                       bb.key_rank, bb.count_next);
+  else if (mode == kGatherKickDrift && bin_next)
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, true>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a,
+                       k, bb.key_rank, bb.count_next);
+  else if (mode == kGatherKickDrift)
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset,
+                       a, k, bb.key_rank, bb.count_next);
+  else
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherFinish, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a,
+                       k, bb.key_rank, bb.count_next);
+}
+
+hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
+                         hipStream_t st) {
+  if (mode != kGatherForce && mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
+  COLA_TZ_DISPATCH(b.tz, gather_tz<TZ>(lat, b, bb, mode, bin_next, a, k, st));
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit_perm(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, float* rho,
+                               float mass, hipStream_t st) {
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_perm<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
+                                            lat, b, src, dst, bb.idx, bb.offset, rho, bb.halo, mass));
+  return hipGetLastError();
+}
+
+template <int TZ>
+static void gather_sorted_tz(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a, KickArgs k,
+                             hipStream_t st) {
+  const dim3 grid(tile_blocks(b)), block(kPartThreads);
+  if (mode == kGatherKickDrift)
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, ss, bb.offset, a, k,
+                       bb.key_rank, bb.count_next);
+  else
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherFinish>), grid, block, 0, st, lat, b, ss, bb.offset, a, k,
+                       bb.key_rank, bb.count_next);
+}
+
+hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a,
+                                KickArgs k, hipStream_t st) {
+  if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
+  COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, ss, bb, mode, a, k, st));
   return hipGetLastError();
 }
 
