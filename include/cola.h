@@ -153,6 +153,31 @@ int cola_finish(cola_plan plan, const cola_particles *p, float *x_out, float *v_
 int cola_run(cola_plan plan, const float *w, const cola_particles *p, float *x_out, float *v_out, void *ws,
              void *stream);
 
+/* Whole run as cola_run (Lagrangian-order steps), also storing the displacement
+ * at every step for the adjoint: ckpt (device, [(n_steps + 1)][3][np^3] floats)
+ * receives s(a_0), s(a_1), ..., s(a_n). */
+int cola_run_checkpointed(cola_plan plan, const float *w, const cola_particles *p, float *x_out, float *v_out,
+                          float *ckpt, void *ws, void *stream);
+
+/* Bytes of workspace cola_run_adjoint needs (more than cola_workspace_bytes). */
+int cola_adjoint_workspace_bytes(cola_plan plan, size_t *bytes);
+
+/* Hand-written adjoint of the whole run.  Given the white noise w (device, np^3)
+ * and the checkpoints ckpt of cola_run_checkpointed for that w, and the gradient
+ * dL_drho (device, nm^3) of a loss L with respect to the final mean-1 CIC density
+ * (cola_density of s(a_n)), writes dL_dw = dL/dw (device, np^3).
+ * The reverse sweep applies, for i = n-1 .. 0, the transpose of the drift and kick
+ * of eq. (KDKALC) with the force recomputed from s(a_i): the transpose of the PM
+ * force is a CIC deposit of the cotangent, the conjugate k-space gradient and a
+ * derivative-weighted CIC gather (CIC deposit and gather are each other's
+ * transposes); then the transpose of the 2LPT initial conditions, where the
+ * second-order source is quadratic in the Hessian of the linear potential.
+ * The final half-kick does not move particles and does not enter.
+ * ws: at least cola_adjoint_workspace_bytes() bytes (not shared with a running
+ * forward call). */
+int cola_run_adjoint(cola_plan plan, const float *w, const float *ckpt, const float *dL_drho, float *dL_dw, void *ws,
+                     void *stream);
+
 /* Forward 3D real FFT on an n^3 grid, n = the plan's np or nm: out[kx][ky][kz]
  * (complex interleaved, kz = 0..n/2-1; the kz = n/2 plane is not produced) =
  * sum_x in[x] exp(-2 pi i k.x / n).  in, out: device, n^3 floats each (out holds

@@ -53,6 +53,9 @@ _PROTOS = {
     "cola_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ColaParticles), _VP, _VP]),
     "cola_finish": (ctypes.c_int, [_VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP]),
     "cola_run": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP]),
+    "cola_run_checkpointed": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP, _VP]),
+    "cola_adjoint_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "cola_run_adjoint": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "cola_fft_r2c": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "cola_fft_c2r": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "cola_plan_set_fft_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
@@ -243,6 +246,24 @@ class Plan:
         _check("cola_trace_read", lib().cola_trace_read(self._c, ms, cnt, n))
         return {lib().cola_trace_stage_name(k).decode(): (ms[k], cnt[k]) for k in range(n) if cnt[k]}
 
+    def run_checkpointed(self, w, p: Particles, x_out, v_out, ckpt, ws, stream=None):
+        cp = p.to_c()
+        _check("cola_run_checkpointed", lib().cola_run_checkpointed(
+            self._c, _ptr(w), ctypes.byref(cp), _ptr(x_out), _ptr(v_out), _ptr(ckpt), _ptr(ws), _stream(stream)))
+
+    def adjoint_workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check("cola_adjoint_workspace_bytes", lib().cola_adjoint_workspace_bytes(self._c, ctypes.byref(b)))
+        return b.value
+
+    def adjoint_workspace(self, device="cuda"):
+        import torch
+        return torch.empty(self.adjoint_workspace_bytes() // 4, dtype=torch.float32, device=device)
+
+    def run_adjoint(self, w, ckpt, dL_drho, dL_dw, ws, stream=None):
+        _check("cola_run_adjoint", lib().cola_run_adjoint(self._c, _ptr(w), _ptr(ckpt), _ptr(dL_drho),
+                                                          _ptr(dL_dw), _ptr(ws), _stream(stream)))
+
     def fft_r2c(self, n: int, inp, out, stream=None):
         _check("cola_fft_r2c", lib().cola_fft_r2c(self._c, n, _ptr(inp), _ptr(out), _stream(stream)))
 
@@ -260,3 +281,50 @@ def run(cfg: Config, w, device="cuda"):
     v = torch.empty_like(x)
     plan.run(w, p, x, v, ws)
     return x, v, p
+
+
+def _autograd_function():
+    import torch
+
+    class ColaDensity(torch.autograd.Function):
+        """Final mean-1 CIC density (nm^3) of a whole COLA run as a function of the
+        white noise w (np^3).  Forward: cola_run_checkpointed + cola_density;
+        backward: cola_run_adjoint (the hand-written adjoint of the whole run)."""
+
+        @staticmethod
+        def forward(ctx, w, plan):
+            cfg = plan.cfg
+            n = cfg.np**3
+            w = w.contiguous()
+            p = Particles.empty(cfg.np, w.device)
+            ws = plan.workspace(w.device)
+            ckpt = torch.empty((cfg.n_steps + 1, 3, n), dtype=torch.float32, device=w.device)
+            x = torch.empty((3, n), dtype=torch.float32, device=w.device)
+            v = torch.empty_like(x)
+            plan.run_checkpointed(w, p, x, v, ckpt, ws)
+            rho = torch.empty(cfg.nm**3, dtype=torch.float32, device=w.device)
+            plan.density(ckpt[cfg.n_steps], rho, ws)
+            ctx.save_for_backward(w, ckpt)
+            ctx.plan = plan
+            return rho
+
+        @staticmethod
+        def backward(ctx, grad_rho):
+            w, ckpt = ctx.saved_tensors
+            plan = ctx.plan
+            aws = plan.adjoint_workspace(w.device)
+            dw = torch.empty_like(w)
+            plan.run_adjoint(w, ckpt, grad_rho.contiguous().float(), dw, aws)
+            return dw, None
+
+    return ColaDensity
+
+
+def cola_density(w, plan: Plan):
+    """Differentiable final density: ColaDensity.apply(w, plan)."""
+    global _COLA_DENSITY
+    try:
+        fn = _COLA_DENSITY
+    except NameError:
+        fn = _COLA_DENSITY = _autograd_function()
+    return fn.apply(w, plan)

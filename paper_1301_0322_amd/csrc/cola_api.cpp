@@ -49,13 +49,14 @@ int hip_status(hipError_t e) {
 enum Stage : int {
   kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStDepositMerge, kStZFwd, kStYFwd, kStXPoisson,
   kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
-  kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kNumStages
+  kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kStAdjKick, kStAdjDeposit, kStAdjFft, kStAdjGather,
+  kStAdjLpt, kStCheckpoint, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
   "bin_count", "bin_scan", "bin_scatter", "deposit", "deposit_merge", "fft_z_fwd", "fft_y_fwd",
   "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
   "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
-  "fft_test"};
+  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint"};
 
 // Records an event pair around launch `fn` when tracing is on.
 template <class F>
@@ -318,6 +319,194 @@ int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out
   }));
 }
 
+// ---------------------------------------------------------------------------------
+// Adjoint of the whole run with respect to the white noise.
+//
+// Workspace layout: [3 nm^3 force meshes | bins | 3 nm^3 adjoint meshes |
+// lam_s, lam_v, lam_s1, lam_s2 (4 x 3 np^3) | 10 np^3 of 2LPT scratch].
+// ---------------------------------------------------------------------------------
+struct AdjLayout {
+  float* amesh[3];
+  float* lam_s;
+  float* lam_v;
+  float* lam_s1;
+  float* lam_s2;
+  float* lpt;       // 10 np^3
+  size_t bytes;
+};
+
+AdjLayout adj_layout(cola_plan p, float* ws) {
+  const long r = cube(p->cfg.nm), n = cube(p->cfg.np);
+  const size_t head = mesh_floats(p) * sizeof(float) + bin_workspace_bytes(n, p->bins);
+  AdjLayout L;
+  float* f = ws ? reinterpret_cast<float*>(reinterpret_cast<char*>(ws) + head) : nullptr;
+  for (int d = 0; d < 3; ++d) L.amesh[d] = f ? f + d * r : nullptr;
+  float* q = f ? f + 3 * r : nullptr;
+  L.lam_s = q;
+  L.lam_v = q ? q + 3 * n : nullptr;
+  L.lam_s1 = q ? q + 6 * n : nullptr;
+  L.lam_s2 = q ? q + 9 * n : nullptr;
+  L.lpt = q ? q + 12 * n : nullptr;
+  L.bytes = head + (3 * (size_t)r + 22 * (size_t)n) * sizeof(float);
+  return L;
+}
+
+// Bins the particles at q + s (no deposit).
+int bin_only(cola_plan p, const float* s, float* ws, hipStream_t st) {
+  const Lattice lat = lattice(p);
+  const BinBuffers bb = bin_buffers(p, ws);
+  COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, p->bins, s, bb, st); }));
+  COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(p->bins, bb, false, st); }));
+  COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
+  return COLA_OK;
+}
+
+// z and y forward passes over nf real fields of an n^3 grid, in place.
+int fwd_zy(cola_plan p, int stage, int n, std::initializer_list<float*> f, const float2* tw, hipStream_t st) {
+  for (float* x : f)
+    COLA_HIP(traced(p, stage, st,
+                    [&] { return launch_zfwd(n, x, reinterpret_cast<float2*>(x), (long)n * n, tw, st); }));
+  return ypass(p, stage, n, -1, fields(f), (int)f.size(), tw, st);
+}
+
+// y and z inverse passes of one field, in place (scale 1).
+int inv_yz(cola_plan p, int stage, int n, float* x, const float2* tw, hipStream_t st) {
+  COLA_TRY(ypass(p, stage, n, 1, fields({x}), 1, tw, st));
+  EpiArgs e{};
+  e.scale = 1.0f;
+  return hip_status(traced(p, stage, st, [&] {
+    return launch_zinv(n, fields({x}), fields({x}), 1, (long)n * n, tw, kEpiStore, e, st);
+  }));
+}
+
+int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_drho, float* dL_dw, float* ws,
+                hipStream_t st) {
+  const int ns = p->cfg.n_steps;
+  const long n = cube(p->cfg.np), n3 = 3 * n;
+  const Lattice lat = lattice(p);
+  const Bins& b = p->bins;
+  const AdjLayout L = adj_layout(p, ws);
+  const float inv_dx = lat.inv_dx;
+  const float mass = (float)std::pow((double)lat.ratio, 3);
+  const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
+  const int nm = p->cfg.nm;
+  for (float* x : {L.lam_s, L.lam_v, L.lam_s1, L.lam_s2})
+    COLA_HIP(traced(p, kStAdjKick, st, [&] { return launch_fill(x, n3, 0.0f, st); }));
+  // dL/ds at the end: derivative of the CIC density of s_n against dL/drho.
+  const float* s_end = ckpt + (long)ns * n3;
+  COLA_TRY(bin_only(p, s_end, ws, st));
+  {
+    AdjGatherArgs ga{};
+    ga.rbar = dL_drho;
+    ga.lam_s = L.lam_s;
+    ga.f1 = 0.0f;
+    ga.f2 = mass * inv_dx;
+    COLA_HIP(traced(p, kStAdjGather, st, [&] { return launch_grad_gather(lat, b, bin_buffers(p, ws), s_end, ga, st); }));
+  }
+  const double kf = 2.0 * M_PI / p->cfg.box;
+  for (int i = ns - 1; i >= 0; --i) {
+    const StepRow& row = p->table[i];
+    const float* s_i = ckpt + (long)i * n3;
+    AdjStepArgs a{};
+    a.alpha = (float)row.alpha;
+    a.beta = (float)row.beta;
+    a.t2d1 = plain ? 0.0f : (float)row.g.t2d1;
+    a.t2d2 = plain ? 0.0f : (float)row.g.t2d2;
+    a.dd1 = plain ? 0.0f : (float)row.dd1;
+    a.dd2 = plain ? 0.0f : (float)row.dd2;
+    COLA_HIP(traced(p, kStAdjKick, st,
+                    [&] { return launch_adj_kick_drift(n3, a, L.lam_s, L.lam_v, L.lam_s1, L.lam_s2, st); }));
+    // recompute the force mesh at s_i (bins for s_i stay valid)
+    COLA_TRY(pm_mesh(p, s_i, row.a, ws, st));
+    // nu_d = mass-weighted CIC deposit of mu_d = lam_v_d
+    const BinBuffers bb = bin_buffers(p, ws);
+    for (int d = 0; d < 3; ++d) {
+      COLA_HIP(traced(p, kStAdjDeposit, st, [&] {
+        return launch_deposit(lat, b, s_i, bb, L.amesh[d], mass, st, L.lam_v + d * n);
+      }));
+      COLA_HIP(traced(p, kStAdjDeposit, st, [&] { return launch_deposit_merge(lat, b, bb, L.amesh[d], st); }));
+    }
+    // rbar = sum_d K_d^T nu_d (conjugate multiplier), into amesh[0]
+    const float2* tw = p->d_tw_nm;
+    COLA_TRY(fwd_zy(p, kStAdjFft, nm, {L.amesh[0], L.amesh[1], L.amesh[2]}, tw, st));
+    MulArgs m{};
+    m.c = (float)(1.5 * p->cfg.omega_m * row.a / (kf * (double)cube(nm)));
+    COLA_HIP(traced(p, kStAdjFft, st, [&] {
+      return launch_xmul_adj(nm, kMulGrad, fields({L.amesh[0], L.amesh[1], L.amesh[2]}), 3,
+                             reinterpret_cast<float2*>(L.amesh[0]), m, tw, st);
+    }));
+    COLA_TRY(inv_yz(p, kStAdjFft, nm, L.amesh[0], tw, st));
+    // lam_s += alpha [ (1/dx) grad(mu . g) + (1/dx) grad(rbar) ]
+    AdjGatherArgs ga{};
+    ga.g0 = ws;
+    ga.g1 = ws + cube(nm);
+    ga.g2 = ws + 2 * cube(nm);
+    ga.mu = L.lam_v;
+    ga.rbar = L.amesh[0];
+    ga.lam_s = L.lam_s;
+    ga.f1 = (float)row.alpha * inv_dx;
+    ga.f2 = (float)row.alpha * inv_dx;
+    COLA_HIP(traced(p, kStAdjGather, st, [&] { return launch_grad_gather(lat, b, bb, s_i, ga, st); }));
+  }
+  // initial state s_0 = D1 s1 + D2 s2 (and, without the LPT frame, v_0 = T[D1] s1 + T[D2] s2)
+  const Growth& g0 = p->g_init;
+  COLA_HIP(traced(p, kStAdjLpt, st, [&] { return launch_axpy(n3, (float)g0.d1, L.lam_s, L.lam_s1, st); }));
+  COLA_HIP(traced(p, kStAdjLpt, st, [&] { return launch_axpy(n3, (float)g0.d2, L.lam_s, L.lam_s2, st); }));
+  if (plain) {
+    COLA_HIP(traced(p, kStAdjLpt, st, [&] { return launch_axpy(n3, (float)g0.td1, L.lam_v, L.lam_s1, st); }));
+    COLA_HIP(traced(p, kStAdjLpt, st, [&] { return launch_axpy(n3, (float)g0.td2, L.lam_v, L.lam_s2, st); }));
+  }
+  // 2LPT VJP.  Recompute the Hessian phi_ab of the linear potential into lpt[3..8].
+  const int np_ = p->cfg.np;
+  const float2* twp = p->d_tw_np;
+  float* sc[10];
+  for (int k = 0; k < 10; ++k) sc[k] = L.lpt + k * n;
+  COLA_HIP(traced(p, kStAdjLpt, st,
+                  [&] { return launch_zfwd(np_, w, reinterpret_cast<float2*>(sc[9]), (long)np_ * np_, twp, st); }));
+  COLA_TRY(ypass(p, kStAdjLpt, np_, -1, fields({sc[9]}), 1, twp, st));
+  MulArgs ml{};
+  ml.kf = (float)kf;
+  ml.tab = p->d_lpt_tab;
+  const FieldPtrs all9 = fields({sc[0], sc[1], sc[2], sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]});
+  COLA_HIP(traced(p, kStAdjLpt, st, [&] {
+    return launch_xmul(np_, kMulLpt1, reinterpret_cast<float2*>(sc[9]), all9, 9, ml, twp, 0, st);
+  }));
+  const FieldPtrs phi = fields({sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]});
+  COLA_TRY(ypass(p, kStAdjLpt, np_, 1, phi, 6, twp, st));
+  EpiArgs e1{};
+  e1.scale = 1.0f;
+  COLA_HIP(traced(p, kStAdjLpt, st,
+                  [&] { return launch_zinv(np_, phi, phi, 6, (long)np_ * np_, twp, kEpiStore, e1, st); }));
+  // sigma = sum_j G_j^T lam_s2_j, G_j the s2 operator (multiplier -i k_j / k^2)
+  float* l2[3] = {L.lam_s2, L.lam_s2 + n, L.lam_s2 + 2 * n};
+  COLA_TRY(fwd_zy(p, kStAdjLpt, np_, {l2[0], l2[1], l2[2]}, twp, st));
+  MulArgs m2{};
+  m2.c = (float)(-1.0 / (kf * (double)n));
+  COLA_HIP(traced(p, kStAdjLpt, st, [&] {
+    return launch_xmul_adj(np_, kMulGrad, fields({l2[0], l2[1], l2[2]}), 3, reinterpret_cast<float2*>(sc[9]), m2,
+                           twp, st);
+  }));
+  COLA_TRY(inv_yz(p, kStAdjLpt, np_, sc[9], twp, st));
+  // tau_ab = dS/dphi_ab^T sigma, in place over phi
+  HessPtrs hp{};
+  for (int k = 0; k < 6; ++k) hp.p[k] = sc[3 + k];
+  COLA_HIP(traced(p, kStAdjLpt, st, [&] { return launch_hessian_adjoint(n, sc[9], hp, st); }));
+  // dL/dw = A^T lam_s1 + H^T tau: transposed LPT multipliers summed in k space
+  float* l1[3] = {L.lam_s1, L.lam_s1 + n, L.lam_s1 + 2 * n};
+  COLA_TRY(fwd_zy(p, kStAdjLpt, np_, {l1[0], l1[1], l1[2]}, twp, st));
+  COLA_TRY(fwd_zy(p, kStAdjLpt, np_, {sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]}, twp, st));
+  const FieldPtrs in9 = fields({l1[0], l1[1], l1[2], sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]});
+  COLA_HIP(traced(p, kStAdjLpt, st, [&] {
+    return launch_xmul_adj(np_, kMulLpt1, in9, 9, reinterpret_cast<float2*>(sc[9]), ml, twp, st);
+  }));
+  COLA_TRY(ypass(p, kStAdjLpt, np_, 1, fields({sc[9]}), 1, twp, st));
+  EpiArgs e2{};
+  e2.scale = 1.0f;
+  return hip_status(traced(p, kStAdjLpt, st, [&] {
+    return launch_zinv(np_, fields({sc[9]}), fields({dL_dw}), 1, (long)np_ * np_, twp, kEpiStore, e2, st);
+  }));
+}
+
 }  // namespace
 
 extern "C" {
@@ -561,6 +750,37 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
     }
   }
   return COLA_OK;
+}
+
+int cola_run_checkpointed(cola_plan p, const float* w, const cola_particles* q, float* x_out, float* v_out,
+                          float* ckpt, void* ws_, void* stream) {
+  COLA_TRY(cola_init_2lpt(p, w, q, ws_, stream));
+  if (!x_out || !v_out || !ckpt) return COLA_ERR_INVALID;
+  float* ws = static_cast<float*>(ws_);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t bytes = 3 * (size_t)cube(p->cfg.np) * sizeof(float);
+  for (int i = 0; i < p->cfg.n_steps; ++i) {
+    float* dst = ckpt + (size_t)i * 3 * cube(p->cfg.np);
+    COLA_HIP(traced(p, kStCheckpoint, st,
+                    [&] { return hipMemcpyAsync(dst, q->s, bytes, hipMemcpyDeviceToDevice, st); }));
+    COLA_TRY(step_impl(p, i, q, ws, st, BinPlan{}));
+  }
+  float* last = ckpt + (size_t)p->cfg.n_steps * 3 * cube(p->cfg.np);
+  COLA_HIP(traced(p, kStCheckpoint, st, [&] { return hipMemcpyAsync(last, q->s, bytes, hipMemcpyDeviceToDevice, st); }));
+  return finish_impl(p, q, x_out, v_out, ws, st, BinPlan{});
+}
+
+int cola_adjoint_workspace_bytes(cola_plan p, size_t* bytes) {
+  if (!p || !bytes) return COLA_ERR_INVALID;
+  *bytes = adj_layout(p, nullptr).bytes;
+  return COLA_OK;
+}
+
+int cola_run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_drho, float* dL_dw, void* ws,
+                     void* stream) {
+  COLA_TRY(check_common(p, ws));
+  if (!w || !ckpt || !dL_drho || !dL_dw) return COLA_ERR_INVALID;
+  return run_adjoint(p, w, ckpt, dL_drho, dL_dw, static_cast<float*>(ws), (hipStream_t)stream);
 }
 
 int cola_fft_r2c(cola_plan p, int32_t n, const float* in, float* out, void* stream) {

@@ -105,8 +105,9 @@ hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t s
 hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
 // Tile deposit (cells written with plain stores, halo faces to the side buffer)
 // followed by the merge of the halo faces.  rho needs no clearing.
+// weight (optional, [np^3] in Lagrangian order): particle p carries mass * weight[p].
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                          hipStream_t st);
+                          hipStream_t st, const float* weight = nullptr);
 hipError_t launch_deposit_merge(Lattice lat, Bins b, BinBuffers bb, float* rho, hipStream_t st);
 
 struct KickArgs {
@@ -157,6 +158,34 @@ hipError_t launch_deposit_perm(Lattice lat, Bins b, SortedState src, SortedState
 // final s, v, x and v_phys in Lagrangian order through a.s, a.v, a.out_a, a.out_b.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a,
                                 KickArgs k, hipStream_t st);
+
+// Adjoint kernels.
+struct AdjGatherArgs {
+  const float* g0;    // force meshes (nullptr: density term only)
+  const float* g1;
+  const float* g2;
+  const float* mu;    // [3][np^3] cotangent of the force (with g)
+  const float* rbar;  // dL/drho mesh
+  float* lam_s;       // [3][np^3] accumulated dL/ds
+  float f1, f2;       // scales of the force-field and density terms (include 1/dx)
+};
+hipError_t launch_grad_gather(Lattice lat, Bins b, BinBuffers bb, const float* s, AdjGatherArgs ga, hipStream_t st);
+struct AdjStepArgs {
+  float alpha, beta, t2d1, t2d2, dd1, dd2;
+};
+hipError_t launch_adj_kick_drift(long n3, AdjStepArgs a, float* lam_s, float* lam_v, float* lam_s1, float* lam_s2,
+                                 hipStream_t st);
+hipError_t launch_axpy(long n, float a, const float* x, float* y, hipStream_t st);
+struct HessPtrs {
+  float* p[6];
+};
+hipError_t launch_hessian_adjoint(long n, const float* sigma, HessPtrs h, hipStream_t st);
+// Transposed x pass: forward x transform of each of nin inputs, multiply by the
+// complex conjugate of the mode's multiplier for that input, sum, inverse x
+// transform into out.  kMulGrad: nin = 3 (conj of c i n_j / n^2); kMulLpt1: nin = 9
+// (conj of the s1_j and phi_ab multipliers).
+hipError_t launch_xmul_adj(int n, int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
+                           hipStream_t st);
 
 hipError_t launch_noise(uint64_t seed, float* w, long count, hipStream_t st);
 

@@ -310,6 +310,75 @@ __global__ __launch_bounds__(T) void k_xmul(const float2* in, FieldPtrs out, int
 }
 
 // ---------------------------------------------------------------------------------
+// Transposed x pass (adjoint of k_xmul): every input is forward transformed along x,
+// multiplied by the complex conjugate of its multiplier and accumulated; the sum is
+// inverse transformed into the single output.
+// ---------------------------------------------------------------------------------
+template <int N, int B, int MODE, int T = col_threads_for(N, B)>
+__global__ __launch_bounds__(T) void k_xmul_adj(FieldPtrs in, int nin, float2* out, MulArgs ma,
+                                                const float2* __restrict__ tw) {
+  constexpr int H = N / 2;
+  constexpr int NT = H / B;
+  constexpr int PER = ceil_div(N * B, T);
+  constexpr bool FULL = (N * B) % T == 0;
+  __shared__ __align__(16) float2 tile[N * B];
+  __shared__ float2 stw[N];
+  load_twiddles(stw, tw, N);
+  const int tc = blockIdx.x % NT;
+  const int y = blockIdx.x / NT;
+  const long inner = (long)N * H;
+  const long origin = (long)y * H + tc * B;
+  const int ny = (y <= H) ? y : y - N;
+  const bool ny_ok = (y != H);
+  float2 acc[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) acc[i] = make_float2(0.f, 0.f);
+  for (int f = 0; f < nin; ++f) {
+    if (f > 0) __syncthreads();
+    col_load<N, B, T>(tile, in.p[f] + origin, inner);
+    __syncthreads();
+    fft_tile<N, B, T, B, 1, false, -1, 1>(tile, stw);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int idx = threadIdx.x + i * T;
+      if (!FULL && idx >= N * B) continue;
+      const int m = idx / B, b = idx % B;
+      const int nx = (m <= H) ? m : m - N;
+      const int nz = tc * B + b;
+      const bool keep = ny_ok && (m != H) && (nx != 0 || ny != 0 || nz != 0);
+      if (!keep) continue;
+      const int nsq = nx * nx + ny * ny + nz * nz;
+      const float2 x = tile[idx];
+      float2 r;
+      if constexpr (MODE == kMulGrad) {
+        const int nj = pick_comp(f, nx, ny, nz);
+        r = mul_si<-1>(c_scale(x, ma.c * (float)nj / (float)nsq));    // conj(i c n_j / n^2) X
+      } else {
+        const float t = ma.tab[nsq];
+        if (f < 3) {
+          const int nj = pick_comp(f, nx, ny, nz);
+          r = mul_si<-1>(c_scale(x, t * (float)nj));                     // conj(i n_j t) X
+        } else {
+          const int na = pick_comp(hess_a(f - 3), nx, ny, nz);
+          const int nb = pick_comp(hess_b(f - 3), nx, ny, nz);
+          r = c_scale(x, ma.kf * t * (float)(na * nb));                   // real multiplier
+        }
+      }
+      acc[i] = c_add(acc[i], r);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int idx = threadIdx.x + i * T;
+    if (FULL || idx < N * B) tile[idx] = acc[i];
+  }
+  __syncthreads();
+  fft_tile<N, B, T, B, 1, false, 1, 1>(tile, stw);
+  col_store<N, B, T>(tile, out + origin, inner);
+}
+
+// ---------------------------------------------------------------------------------
 // Host dispatch.
 // ---------------------------------------------------------------------------------
 #define COLA_FOR_EACH_SIZE(X) \
@@ -418,6 +487,19 @@ static hipError_t xmul_t(int mode, const float2* in, FieldPtrs out, int nout, Mu
 }
 
 template <int N>
+static hipError_t xmul_adj_t(int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
+                             hipStream_t st) {
+  constexpr int B = xmul_width<N>();
+  constexpr int T = col_threads_for(N, B);
+  dim3 grid(N * ((N / 2) / B));
+  if (mode == kMulGrad)
+    hipLaunchKernelGGL((k_xmul_adj<N, B, kMulGrad>), grid, dim3(T), 0, st, in, nin, out, m, tw);
+  else
+    hipLaunchKernelGGL((k_xmul_adj<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, nin, out, m, tw);
+  return hipGetLastError();
+}
+
+template <int N>
 static bool width_ok(int w) {
   switch (w) {
     case 0: return true;
@@ -484,6 +566,19 @@ hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n
 #define COLA_CASE(N) \
   case N:            \
     return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, st);
+    COLA_FOR_EACH_SIZE(COLA_CASE)
+#undef COLA_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_xmul_adj(int n, int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
+                           hipStream_t st) {
+  switch (n) {
+#define COLA_CASE(N) \
+  case N:            \
+    return xmul_adj_t<N>(mode, in, nin, out, m, tw, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:

@@ -217,7 +217,8 @@ template <int TZ>
 __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
                                                                 const int* __restrict__ idx,
                                                                 const int* __restrict__ offset, float* __restrict__ rho,
-                                                                float* __restrict__ halo, float mass) {
+                                                                float* __restrict__ halo, float mass,
+                                                                const float* __restrict__ weight) {
   using D = TileDims<TZ>;
   __shared__ float tile[D::EXT];
   TileGeom g;
@@ -238,11 +239,12 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bin
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (!ok[u]) continue;
+      const float mw = weight ? mass * weight[idx[i + u * kPartThreads]] : mass;
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          const float wab = mass * (a ? fr[u][0] : 1.f - fr[u][0]) * (b ? fr[u][1] : 1.f - fr[u][1]);
+          const float wab = mw * (a ? fr[u][0] : 1.f - fr[u][0]) * (b ? fr[u][1] : 1.f - fr[u][1]);
           float* row = tile + ((lc[u][0] + a) * D::EY + lc[u][1] + b) * D::EZ + lc[u][2];
           atomicAdd(row, wab * (1.f - fr[u][2]));
           atomicAdd(row + 1, wab * fr[u][2]);
@@ -393,6 +395,83 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
       const int rank = wave_rank(act, bin, count_next);
       if (act) key_rank_next[p] = make_int2(bin, rank);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// Adjoint gather: the derivative of CIC interpolation with respect to the particle
+// position.  For a mesh field F and a particle with base cell c and fractions f,
+//   dF_interp/du_x = sum_{b,c} wy_b wz_c (F[c+1,b,c] - F[c,b,c])   (likewise y, z),
+// and u = x / dx.  Per particle the kernel adds to lam_s
+//   f1 * grad(sum_d mu_d g_d) + f2 * grad(rbar)
+// (f1, f2 include 1/dx): the force-field term of the force VJP (when g, mu are
+// given) and the density term through rbar = dL/drho.
+// ---------------------------------------------------------------------------------
+template <int TZ>
+__global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins bins, const int* __restrict__ idx,
+                                                              const int* __restrict__ offset,
+                                                              const float* __restrict__ s, AdjGatherArgs ga) {
+  using D = TileDims<TZ>;
+  __shared__ float tile[4 * D::EXT];
+  TileGeom t;
+  if (!tile_geom<TZ>(bins, t)) return;
+  const int nm = lat.nm;
+  const bool with_g = ga.g0 != nullptr;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) {
+    const int z = i % D::EZ, r = i / D::EZ;
+    const int y = r % D::EY, x = r / D::EY;
+    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
+    gx -= (gx >= nm) ? nm : 0;
+    gy -= (gy >= nm) ? nm : 0;
+    gz -= (gz >= nm) ? nm : 0;
+    const long gi = ((long)gx * nm + gy) * nm + gz;
+    tile[3 * D::EXT + i] = ga.rbar[gi];
+    if (with_g) {
+      tile[i] = ga.g0[gi];
+      tile[D::EXT + i] = ga.g1[gi];
+      tile[2 * D::EXT + i] = ga.g2[gi];
+    }
+  }
+  __syncthreads();
+  const long n = lat.npart;
+  const int beg = offset[t.bin], end = offset[t.bin + 1];
+  for (int i = beg + threadIdx.x; i < end; i += kPartThreads) {
+    const unsigned p = (unsigned)idx[i];
+    float sv[3], fr[3];
+    int lc[3];
+    if (!local_stencil<TZ>(lat, t, s, p, sv, lc, fr)) continue;   // cannot happen
+    float mu[3] = {0.f, 0.f, 0.f};
+    if (with_g) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) mu[d] = ga.mu[d * n + p];
+    }
+    // corner values of H = sum_d mu_d g_d and of rbar
+    float h[2][2][2], r[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2] + c;
+          r[a][b][c] = tile[3 * D::EXT + o];
+          h[a][b][c] = with_g ? mu[0] * tile[o] + mu[1] * tile[D::EXT + o] + mu[2] * tile[2 * D::EXT + o] : 0.f;
+        }
+    const float w[3][2] = {{1.f - fr[0], fr[0]}, {1.f - fr[1], fr[1]}, {1.f - fr[2], fr[2]}};
+    float gh[3] = {0.f, 0.f, 0.f}, gr[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        gh[0] += w[1][a] * w[2][b] * (h[1][a][b] - h[0][a][b]);
+        gr[0] += w[1][a] * w[2][b] * (r[1][a][b] - r[0][a][b]);
+        gh[1] += w[0][a] * w[2][b] * (h[a][1][b] - h[a][0][b]);
+        gr[1] += w[0][a] * w[2][b] * (r[a][1][b] - r[a][0][b]);
+        gh[2] += w[0][a] * w[1][b] * (h[a][b][1] - h[a][b][0]);
+        gr[2] += w[0][a] * w[1][b] * (r[a][b][1] - r[a][b][0]);
+      }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) ga.lam_s[d * n + p] += ga.f1 * gh[d] + ga.f2 * gr[d];
   }
 }
 
@@ -675,9 +754,9 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 }
 
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                          hipStream_t st) {
+                          hipStream_t st, const float* weight) {
   COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_tiles<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
-                                            lat, b, s, bb.idx, bb.offset, rho, bb.halo, mass));
+                                            lat, b, s, bb.idx, bb.offset, rho, bb.halo, mass, weight));
   return hipGetLastError();
 }
 
@@ -735,6 +814,73 @@ hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState ss, BinBuffers 
                                 KickArgs k, hipStream_t st) {
   if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
   COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, ss, bb, mode, a, k, st));
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_gather(Lattice lat, Bins b, BinBuffers bb, const float* s, AdjGatherArgs ga, hipStream_t st) {
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_grad_gather<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st, lat, b,
+                                            bb.idx, bb.offset, s, ga));
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------
+// Elementwise adjoint updates over [3][n] particle arrays.
+// ---------------------------------------------------------------------------------
+// Reverse of v' = v + alpha (F - c1 s1 - c2 s2), s' = s + beta v' + d1 s1 + d2 s2:
+//   mu = lam_v + beta lam_s;  lam_s1 += d1 lam_s - alpha c1 mu;
+//   lam_s2 += d2 lam_s - alpha c2 mu;  lam_v = mu  (lam_s is updated by the gather).
+__global__ __launch_bounds__(kPartThreads) void k_adj_kick_drift(long n3, AdjStepArgs a, float* __restrict__ lam_s,
+                                                                 float* __restrict__ lam_v, float* __restrict__ lam_s1,
+                                                                 float* __restrict__ lam_s2) {
+  const long i = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  if (i >= n3) return;
+  const float ls = lam_s[i];
+  const float mu = lam_v[i] + a.beta * ls;
+  lam_s1[i] += a.dd1 * ls - a.alpha * a.t2d1 * mu;
+  lam_s2[i] += a.dd2 * ls - a.alpha * a.t2d2 * mu;
+  lam_v[i] = mu;
+}
+
+hipError_t launch_adj_kick_drift(long n3, AdjStepArgs a, float* lam_s, float* lam_v, float* lam_s1, float* lam_s2,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_kick_drift, dim3((unsigned)((n3 + kPartThreads - 1) / kPartThreads)), dim3(kPartThreads),
+                     0, st, n3, a, lam_s, lam_v, lam_s1, lam_s2);
+  return hipGetLastError();
+}
+
+// y += a x over n floats
+__global__ __launch_bounds__(kPartThreads) void k_axpy(long n, float a, const float* __restrict__ x,
+                                                       float* __restrict__ y) {
+  const long i = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+hipError_t launch_axpy(long n, float a, const float* x, float* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3((unsigned)((n + kPartThreads - 1) / kPartThreads)), dim3(kPartThreads), 0, st, n, a,
+                     x, y);
+  return hipGetLastError();
+}
+
+// Adjoint of S = sum_{i<j} (phi_ii phi_jj - phi_ij^2) with cotangent sigma, in place:
+// phi_aa <- sigma (tr phi - phi_aa), phi_ab <- -2 sigma phi_ab.  phi order xx yy zz xy yz zx.
+__global__ __launch_bounds__(kPartThreads) void k_hessian_adjoint(long n, const float* __restrict__ sigma,
+                                                                  HessPtrs h) {
+  const long i = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  if (i >= n) return;
+  const float sg = sigma[i];
+  const float xx = h.p[0][i], yy = h.p[1][i], zz = h.p[2][i];
+  const float tr = xx + yy + zz;
+  h.p[0][i] = sg * (tr - xx);
+  h.p[1][i] = sg * (tr - yy);
+  h.p[2][i] = sg * (tr - zz);
+  h.p[3][i] = -2.f * sg * h.p[3][i];
+  h.p[4][i] = -2.f * sg * h.p[4][i];
+  h.p[5][i] = -2.f * sg * h.p[5][i];
+}
+
+hipError_t launch_hessian_adjoint(long n, const float* sigma, HessPtrs h, hipStream_t st) {
+  hipLaunchKernelGGL(k_hessian_adjoint, dim3((unsigned)((n + kPartThreads - 1) / kPartThreads)), dim3(kPartThreads), 0,
+                     st, n, sigma, h);
   return hipGetLastError();
 }
 

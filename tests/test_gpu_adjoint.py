@@ -1,0 +1,105 @@
+"""GPU adjoint of the whole run (cola_run_adjoint) against the FP64 oracle.
+
+Loss L = sum_c (rho_c - rho_target_c)^2 of the final CIC density, gradient with
+respect to the white noise w.  References: the oracle's FP64 autograd gradient
+(pinned against its own finite differences on the CPU) and central finite
+differences of the FP64 oracle along random unit directions.
+Bars: FP32 forward and adjoint through 10 steps: rel L2 <= 1e-3 against the
+reference gradient; per-direction derivative within 1e-3 of the FP64 difference
+quotient (relative to the gradient norm).
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1301_0322_amd as cola
+from oracle import cola as ocola
+from oracle import cosmology as cosmo
+from oracle import lpt, pm
+from oracle.fourier import F64
+from paper_1301_0322_amd import inputs
+from tests.gpu_util import announce, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_loss(w64, ocfg, target):
+    s1, s2 = lpt.lpt_from_noise(w64, ocfg)
+    _, _, s = ocola.evolve(s1, s2, ocfg)
+    rho = pm.cic_deposit(s, ocfg.np_side, ocfg.nm_side, ocfg.box)
+    return ((rho - target) ** 2).sum()
+
+
+def _gpu_grad(cfg, w, target):
+    with cola.Plan(cfg) as plan:
+        wd = dev(w).requires_grad_(True)
+        rho = cola.cola_density(wd, plan)
+        loss = ((rho - dev(target.reshape(-1).astype(np.float32))) ** 2).sum()
+        loss.backward()
+        return host(wd.grad), float(loss.item()), host(rho)
+
+
+@pytest.mark.parametrize("np_side,nm,seed", [(16, 32, 11), (32, 64, 11)])
+def test_adjoint_matches_oracle_autograd(np_side, nm, seed):
+    cfg = cola.Config(np=np_side, nm=nm)
+    ocfg = cosmo.Config(np_side=np_side, nm_side=nm)
+    w = inputs.white_noise(np_side, seed)
+    # target: the final density of a second realization
+    wt = inputs.white_noise(np_side, seed + 1).astype(np.float64)
+    s1t, s2t = lpt.lpt_from_noise(wt, ocfg)
+    _, _, st = ocola.evolve(s1t, s2t, ocfg)
+    target = pm.cic_deposit(st, np_side, nm, ocfg.box).numpy()
+    announce(f"adjoint np={np_side} nm={nm}")
+    g_gpu, loss_gpu, rho = _gpu_grad(cfg, w, target)
+    w64 = torch.tensor(w.astype(np.float64), requires_grad=True)
+    loss = _oracle_loss(w64, ocfg, torch.tensor(target, dtype=F64))
+    (g_ref,) = torch.autograd.grad(loss, w64)
+    assert loss_gpu == pytest.approx(loss.item(), rel=1e-3)
+    assert rel_l2(g_gpu, g_ref.numpy()) < 1e-3
+
+
+def test_adjoint_matches_finite_differences():
+    np_side, nm = 32, 64
+    cfg = cola.Config(np=np_side, nm=nm)
+    ocfg = cosmo.Config(np_side=np_side, nm_side=nm)
+    w = inputs.white_noise(np_side, 11)
+    rng = np.random.default_rng(12)
+    target = 1.0 + 0.5 * rng.standard_normal((nm, nm, nm))
+    announce("adjoint vs FD 32/64")
+    g_gpu, _, _ = _gpu_grad(cfg, w, target)
+    gnorm = np.linalg.norm(g_gpu)
+    w0 = torch.tensor(w.astype(np.float64))
+    tt = torch.tensor(target, dtype=F64)
+    eps = 1e-4
+    for k in range(8):
+        d = rng.standard_normal(np_side**3)
+        d /= np.linalg.norm(d)
+        dt = torch.tensor(d)
+        fd = (_oracle_loss(w0 + eps * dt, ocfg, tt) - _oracle_loss(w0 - eps * dt, ocfg, tt)).item() / (2 * eps)
+        assert abs(float(g_gpu.astype(np.float64) @ d) - fd) <= 1e-3 * gnorm, k
+
+
+def test_adjoint_full_size_directional_derivative():
+    """128^3 particles / 256^3 mesh: the adjoint's directional derivative against a
+    central difference of the GPU forward itself (FP32, so a loose bar)."""
+    np_side, nm = 128, 256
+    cfg = cola.Config(np=np_side, nm=nm)
+    w = inputs.white_noise(np_side, 11)
+    wt = inputs.white_noise(np_side, 12)
+    announce("adjoint 128/256")
+    with cola.Plan(cfg) as plan:
+        rho_t = cola.cola_density(dev(wt), plan).detach()
+        wd = dev(w).requires_grad_(True)
+        rho = cola.cola_density(wd, plan)
+        ((rho - rho_t) ** 2).sum().backward()
+        g = wd.grad.double()
+        # Along the gradient itself the derivative is |g|, far above the FP32 noise of
+        # the forward; the central difference converges to it as eps shrinks (3e-2:
+        # 6% low, 1e-3: 0.1%), so eps = 1e-3 with a 1% bar.
+        d = g / g.norm()
+        eps = 1e-3
+        with torch.no_grad():
+            lp = ((cola.cola_density((wd + eps * d).float(), plan) - rho_t).double() ** 2).sum()
+            lm = ((cola.cola_density((wd - eps * d).float(), plan) - rho_t).double() ** 2).sum()
+        fd = ((lp - lm) / (2 * eps)).item()
+        assert g.norm().item() == pytest.approx(fd, rel=1e-2)
