@@ -127,6 +127,97 @@ def cpu_baseline(np_side: int, nm: int, box: float, seed: int) -> dict:
     }
 
 
+ENSEMBLE = [(64, 128, 16), (96, 192, 16), (128, 256, 16)]   # (np, nm, members), 100 Mpc/h
+
+
+def timed(fn, stream, reps=1):
+    """Milliseconds of fn() per repetition, HIP events on the launch stream."""
+    import torch
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        fn()
+    b.record(stream)
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_ensemble(stream) -> dict:
+    """48 uneven-size realizations: one graph launch against the same runs issued
+    one after another."""
+    import torch
+    import paper_1301_0322_amd as cola
+    plans, noises = [], []
+    seed = 1
+    for np_side, nm, count in ENSEMBLE:
+        for _ in range(count):
+            pl = cola.Plan(cola.Config(np=np_side, nm=nm))
+            w = torch.empty(np_side**3, dtype=torch.float32, device="cuda")
+            pl.noise(seed, w)
+            plans.append(pl)
+            noises.append(w)
+            seed += 1
+    # tune each size once, share the choice
+    tuned = {}
+    for pl in plans:
+        key = (pl.cfg.np, pl.cfg.nm)
+        if key not in tuned:
+            p = cola.Particles.empty(pl.cfg.np)
+            pl.init_2lpt(noises[plans.index(pl)], p, pl.workspace())
+            pl.autotune(p, None)
+            tuned[key] = pl.get_tuning()
+        y, x, tz = tuned[key]
+        pl.set_fft_tile(0, y)
+        pl.set_fft_tile(1, x)
+        pl.set_bin_depth(tz)
+    ens = cola.Ensemble(plans, noises)
+    ens.launch()
+    torch.cuda.synchronize()
+    t_graph = timed(ens.launch, stream, reps=2)
+
+    def sequential():
+        for k, pl in enumerate(plans):
+            pl.run(noises[k], ens.particles[k], ens.x[k], ens.v[k], ens.ws[k])
+    sequential()
+    torch.cuda.synchronize()
+    t_seq = timed(sequential, stream, reps=2)
+    work = sum(pl.cfg.np**3 * pl.cfg.n_steps for pl in plans)
+    ens.close()
+    return {"members": len(plans), "sizes": [list(e) for e in ENSEMBLE], "graph_ms": t_graph,
+            "sequential_ms": t_seq, "graph_particle_steps_per_s": work / (t_graph * 1e-3),
+            "sequential_particle_steps_per_s": work / (t_seq * 1e-3), "speedup": t_seq / t_graph}
+
+
+def bench_adjoint(stream) -> dict:
+    """128^3 / 256^3 differentiable run: forward with checkpoints + density against
+    the hand-written adjoint; loss = sum (delta - delta_target)^2."""
+    import torch
+    import paper_1301_0322_amd as cola
+    np_side, nm = 128, 256
+    plan = cola.Plan(cola.Config(np=np_side, nm=nm))
+    w = torch.empty(np_side**3, dtype=torch.float32, device="cuda")
+    wt = torch.empty_like(w)
+    plan.noise(11, w)
+    plan.noise(12, wt)
+    rho_t = cola.cola_density(wt, plan).detach()
+    wd = w.clone().requires_grad_(True)
+
+    def fwd():
+        return cola.cola_density(wd, plan)
+
+    def fwd_bwd():
+        rho = fwd()
+        ((rho - rho_t) ** 2).sum().backward()
+    fwd_bwd()
+    torch.cuda.synchronize()
+    t_f = timed(lambda: fwd(), stream, reps=2)
+    t_fb = timed(fwd_bwd, stream, reps=2)
+    return {"config": f"{np_side}^3 particles / {nm}^3 mesh, 10 steps, loss sum (delta - delta_target)^2",
+            "forward_ms": t_f, "forward_backward_ms": t_fb, "adjoint_ms": t_fb - t_f,
+            "adjoint_over_forward": (t_fb - t_f) / t_f, "fwd_bwd_over_fwd": t_fb / t_f}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +225,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c1", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -156,6 +250,12 @@ def main() -> int:
     x = torch.empty((3, np_side**3), dtype=torch.float32, device="cuda")
     v = torch.empty_like(x)
     stream = torch.cuda.current_stream()
+    tuning = None
+    if not args.no_autotune:
+        plan.init_2lpt(w, p, ws)
+        plan.autotune(p, None)
+        tuning = dict(zip(("y_width", "x_width", "bin_depth"), plan.get_tuning()))
+        ws = plan.workspace()
 
     for _ in range(args.warmup):
         plan.run(w, p, x, v, ws)
@@ -224,7 +324,16 @@ def main() -> int:
         "pm_step": {"ms": pm_step_ms, "particle_steps_per_s": np_side**3 / (pm_step_ms * 1e-3),
                     "b_alg_bytes": b_alg, "hbm_frac": b_alg / (pm_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)},
         "stages_per_run": per_run,
+        "tuning": tuning,
     }
+    if not args.no_ensemble:
+        del ws
+        torch.cuda.empty_cache()
+        out["ensemble"] = bench_ensemble(stream)
+        torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = bench_adjoint(stream)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(np_side, nm, box, seed)
     print(json.dumps(out), flush=True)

@@ -79,6 +79,7 @@ typedef struct {
 } cola_config;
 
 typedef struct cola_plan_s *cola_plan;
+typedef struct cola_ensemble_s *cola_ensemble;
 
 /* Device particle arrays, each [3][np^3] floats (layout above), caller-owned. */
 typedef struct {
@@ -195,6 +196,45 @@ int cola_fft_c2r(cola_plan plan, int32_t n, const float *in, float *out, void *s
  * the built-in default.  COLA_ERR_UNSUPPORTED_SIZE if the width does not divide
  * nm/2 or the tile would exceed 64 KB of LDS.  Host-only. */
 int cola_plan_set_fft_tile(cola_plan plan, int32_t pass, int32_t width);
+
+/* Depth in cells (8, 16 or 32) of the 8 x 8 x depth mesh tiles by which particles
+ * are binned for the deposit and gather (a tuning knob; results agree up to FP32
+ * summation order).  Call cola_workspace_bytes again afterwards.  Host-only. */
+int cola_plan_set_bin_depth(cola_plan plan, int32_t depth);
+
+/* Current tuning: y-pass and x-pass tile widths (0 = built-in default) and bin
+ * depth.  Host-only. */
+int cola_plan_get_tuning(cola_plan plan, int32_t *y_width, int32_t *x_width, int32_t *bin_depth);
+
+/* Autotuner: picks the FFT tile widths and the bin depth of the plan by timing one
+ * PM force evaluation of the particles p (device) for every valid combination
+ * (HIP events on stream, best of two repetitions) and keeps the fastest.  With
+ * cache_path (a text file, may be NULL) a previous choice for the same
+ * (np, nm, GPU architecture) is reused without measuring, and a new choice is
+ * appended.  *used_cache (nullable) reports whether the cache answered.  ws holds
+ * ws_bytes bytes (cola_tuning_workspace_bytes() lets every depth be tried; depths
+ * whose binning buffers would not fit are skipped).  Call cola_workspace_bytes
+ * again afterwards.  This call synchronises stream.
+ * Results of the tuned plan agree with the default up to FP32 rounding. */
+int cola_autotune(cola_plan plan, const cola_particles *p, void *ws, size_t ws_bytes, void *stream,
+                  const char *cache_path, int32_t *used_cache);
+/* Workspace bytes that let cola_autotune try every tile depth. */
+int cola_tuning_workspace_bytes(cola_plan plan, size_t *bytes);
+
+/* Ensemble of independent realizations (possibly of different sizes), the
+ * paper's intended use (Section 1: ensembles of mock catalogs).  Captures the
+ * whole cola_run of every member k (plans[k], noise w[k], particles p[k], outputs
+ * x_out[k], v_out[k], workspace ws[k]) once into a single hipGraph in which each
+ * member is an independent branch, so small members run concurrently; members
+ * must not share particles, outputs or workspaces.  Pointers are baked into the
+ * graph: the buffers must stay allocated while the ensemble exists.  Plans must
+ * have tracing off.  Creation uses private streams and does not run the graph. */
+int cola_ensemble_create(int32_t n, const cola_plan *plans, const float *const *w, const cola_particles *p,
+                         float *const *x_out, float *const *v_out, void *const *ws, cola_ensemble *out);
+/* Runs every member once: a single graph launch on stream. */
+int cola_ensemble_launch(cola_ensemble ens, void *stream);
+/* Frees the graph (the caller synchronises any launch first).  NULL is accepted. */
+int cola_ensemble_destroy(cola_ensemble ens);
 
 /* Stage tracing (for profiling; off by default).  When enabled, every kernel launch
  * of the calls above is bracketed by a pair of hipEvents recorded on the launch

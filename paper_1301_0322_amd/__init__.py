@@ -59,6 +59,17 @@ _PROTOS = {
     "cola_fft_r2c": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "cola_fft_c2r": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "cola_plan_set_fft_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
+    "cola_plan_set_bin_depth": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "cola_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "cola_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(ColaParticles), _VP, ctypes.c_size_t, _VP,
+                                     ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
+    "cola_tuning_workspace_bytes": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_size_t)]),
+    "cola_ensemble_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                            ctypes.POINTER(ColaParticles), ctypes.POINTER(_VP),
+                                            ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
+    "cola_ensemble_launch": (ctypes.c_int, [_VP, _VP]),
+    "cola_ensemble_destroy": (ctypes.c_int, [_VP]),
     "cola_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
     "cola_trace_read": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_int32]),
@@ -235,6 +246,30 @@ class Plan:
     def set_fft_tile(self, pass_: int, width: int):
         _check("cola_plan_set_fft_tile", lib().cola_plan_set_fft_tile(self._c, pass_, width))
 
+    def set_bin_depth(self, depth: int):
+        _check("cola_plan_set_bin_depth", lib().cola_plan_set_bin_depth(self._c, depth))
+
+    def get_tuning(self):
+        y, x, tz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check("cola_plan_get_tuning", lib().cola_plan_get_tuning(self._c, ctypes.byref(y), ctypes.byref(x),
+                                                                  ctypes.byref(tz)))
+        return y.value, x.value, tz.value
+
+    def autotune(self, p: Particles, ws, cache_path=None, stream=None) -> bool:
+        """Times the tile shapes on the PM force of p and keeps the fastest; True if
+        the choice came from cache_path."""
+        import torch
+        need = ctypes.c_size_t()
+        _check("cola_tuning_workspace_bytes", lib().cola_tuning_workspace_bytes(self._c, ctypes.byref(need)))
+        if ws is None or ws.numel() * 4 < need.value:
+            ws = torch.empty(need.value // 4 + 1, dtype=torch.float32, device=p.s.device)
+        cp = p.to_c()
+        used = ctypes.c_int32()
+        path = cache_path.encode() if cache_path else None
+        _check("cola_autotune", lib().cola_autotune(self._c, ctypes.byref(cp), _ptr(ws), ws.numel() * 4,
+                                                    _stream(stream), path, ctypes.byref(used)))
+        return bool(used.value)
+
     def trace_enable(self, enable: bool = True):
         _check("cola_trace_enable", lib().cola_trace_enable(self._c, int(enable)))
 
@@ -269,6 +304,45 @@ class Plan:
 
     def fft_c2r(self, n: int, inp, out, stream=None):
         _check("cola_fft_c2r", lib().cola_fft_c2r(self._c, n, _ptr(inp), _ptr(out), _stream(stream)))
+
+
+class Ensemble:
+    """Whole runs of several plans captured once into one hipGraph (one branch per
+    member) and replayed with ``launch()``.  Buffers are allocated here and kept
+    alive with the graph: ``x[k]``, ``v[k]``, ``particles[k]``."""
+
+    def __init__(self, plans, noises, device="cuda"):
+        import torch
+        self.plans = list(plans)
+        self.noises = [w.contiguous() for w in noises]
+        self.particles = [Particles.empty(pl.cfg.np, device) for pl in self.plans]
+        self.ws = [pl.workspace(device) for pl in self.plans]
+        self.x = [torch.empty((3, pl.cfg.np**3), dtype=torch.float32, device=device) for pl in self.plans]
+        self.v = [torch.empty_like(x) for x in self.x]
+        n = len(self.plans)
+        arr = lambda vals: (_VP * n)(*vals)
+        parts = (ColaParticles * n)(*[p.to_c() for p in self.particles])
+        self._c = _VP()
+        _check("cola_ensemble_create", lib().cola_ensemble_create(
+            n, arr([pl._c for pl in self.plans]), arr([_ptr(w) for w in self.noises]), parts,
+            arr([_ptr(x) for x in self.x]), arr([_ptr(v) for v in self.v]), arr([_ptr(w) for w in self.ws]),
+            ctypes.byref(self._c)))
+
+    def launch(self, stream=None):
+        _check("cola_ensemble_launch", lib().cola_ensemble_launch(self._c, _stream(stream)))
+
+    def close(self):
+        if self._c:
+            import torch
+            torch.cuda.synchronize()
+            lib().cola_ensemble_destroy(self._c)
+            self._c = _VP()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run(cfg: Config, w, device="cuda"):

@@ -2,7 +2,10 @@
 // entry points that drive the gfx950 kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <string>
 #include <cstring>
 #include <new>
 #include <utility>
@@ -820,6 +823,218 @@ int cola_plan_set_fft_tile(cola_plan p, int32_t pass, int32_t width) {
   if (!p || pass < 0 || pass > 1) return COLA_ERR_INVALID;
   if (!fft_width_supported(p->cfg.nm, width)) return COLA_ERR_UNSUPPORTED_SIZE;
   p->fft_width[pass] = width;
+  return COLA_OK;
+}
+
+int cola_plan_set_bin_depth(cola_plan p, int32_t tz) {
+  if (!p || (tz != 8 && tz != 16 && tz != 32)) return COLA_ERR_INVALID;
+  if (p->cfg.nm % tz) return COLA_ERR_UNSUPPORTED_SIZE;
+  p->bins = make_bins(p->cfg.nm, tz);
+  return COLA_OK;
+}
+
+int cola_plan_get_tuning(cola_plan p, int32_t* y_width, int32_t* x_width, int32_t* bin_depth) {
+  if (!p || !y_width || !x_width || !bin_depth) return COLA_ERR_INVALID;
+  *y_width = p->fft_width[0];
+  *x_width = p->fft_width[1];
+  *bin_depth = p->bins.tz;
+  return COLA_OK;
+}
+
+int cola_tuning_workspace_bytes(cola_plan p, size_t* bytes) {
+  if (!p || !bytes) return COLA_ERR_INVALID;
+  size_t worst = 0;
+  for (int tz : {8, 16, 32})
+    if (p->cfg.nm % tz == 0) worst = std::max(worst, bin_workspace_bytes(cube(p->cfg.np), make_bins(p->cfg.nm, tz)));
+  *bytes = mesh_floats(p) * sizeof(float) + worst;
+  return COLA_OK;
+}
+
+int cola_autotune(cola_plan p, const cola_particles* q, void* ws_, size_t ws_bytes, void* stream,
+                  const char* cache_path, int32_t* used_cache) {
+  COLA_TRY(check_common(p, ws_));
+  COLA_TRY(check_particles(q));
+  if (used_cache) *used_cache = 0;
+  hipStream_t st = (hipStream_t)stream;
+  int dev = 0;
+  COLA_HIP(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  COLA_HIP(hipGetDeviceProperties(&prop, dev));
+  char key[256];
+  std::snprintf(key, sizeof(key), "np=%d nm=%d arch=%s", p->cfg.np, p->cfg.nm, prop.gcnArchName);
+  // cached choice?
+  if (cache_path) {
+    if (FILE* fh = std::fopen(cache_path, "r")) {
+      char line[512];
+      while (std::fgets(line, sizeof(line), fh)) {
+        int y = 0, x = 0, tz = 0;
+        char k[256] = {0};
+        if (std::sscanf(line, "%255[^|]| y=%d x=%d tz=%d", k, &y, &x, &tz) == 4) {
+          std::string ks(k);
+          while (!ks.empty() && ks.back() == ' ') ks.pop_back();
+          if (ks == key && fft_width_supported(p->cfg.nm, y) && fft_width_supported(p->cfg.nm, x) &&
+              p->cfg.nm % tz == 0 && (tz == 8 || tz == 16 || tz == 32)) {
+            std::fclose(fh);
+            p->fft_width[0] = y;
+            p->fft_width[1] = x;
+            p->bins = make_bins(p->cfg.nm, tz);
+            if (used_cache) *used_cache = 1;
+            return COLA_OK;
+          }
+        }
+      }
+      std::fclose(fh);
+    }
+  }
+  // Measure every valid combination on the PM force of the given particles; tile
+  // depths whose binning buffers would not fit the given workspace are skipped.
+  const bool was_tracing = p->trace;
+  if (ws_bytes < mesh_floats(p) * sizeof(float)) return COLA_ERR_INVALID;
+  const size_t bin_cap = ws_bytes - mesh_floats(p) * sizeof(float);
+  p->trace = false;
+  hipEvent_t e0, e1;
+  COLA_HIP(hipEventCreate(&e0));
+  COLA_HIP(hipEventCreate(&e1));
+  float* ws = static_cast<float*>(ws_);
+  float best = 1e30f;
+  int by = 0, bx = 0, btz = p->bins.tz;
+  const int default_tz = p->bins.tz;
+  int rc = COLA_OK;
+  const int widths[] = {4, 8, 16};
+  (void)default_tz;
+  for (int tz : {8, 16, 32}) {
+    if (p->cfg.nm % tz) continue;
+    if (bin_workspace_bytes(cube(p->cfg.np), make_bins(p->cfg.nm, tz)) > bin_cap) continue;
+    p->bins = make_bins(p->cfg.nm, tz);
+    for (int y : widths) {
+      if (!fft_width_supported(p->cfg.nm, y)) continue;
+      for (int x : widths) {
+        if (!fft_width_supported(p->cfg.nm, x)) continue;
+        p->fft_width[0] = y;
+        p->fft_width[1] = x;
+        float t_min = 1e30f;
+        for (int rep = 0; rep < 3 && rc == COLA_OK; ++rep) {
+          rc = hip_status(hipEventRecord(e0, st));
+          if (rc == COLA_OK) rc = pm_mesh(p, q->s, p->table[0].a, ws, st);
+          if (rc == COLA_OK) rc = hip_status(hipEventRecord(e1, st));
+          if (rc == COLA_OK) rc = hip_status(hipEventSynchronize(e1));
+          float ms = 0.f;
+          if (rc == COLA_OK) rc = hip_status(hipEventElapsedTime(&ms, e0, e1));
+          if (rep > 0) t_min = std::min(t_min, ms);
+        }
+        if (rc != COLA_OK) break;
+        if (t_min < best) {
+          best = t_min;
+          by = y;
+          bx = x;
+          btz = tz;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->trace = was_tracing;
+  p->fft_width[0] = by;
+  p->fft_width[1] = bx;
+  p->bins = make_bins(p->cfg.nm, btz);
+  if (rc != COLA_OK) return rc;
+  if (cache_path) {
+    if (FILE* fh = std::fopen(cache_path, "a")) {
+      std::fprintf(fh, "%s | y=%d x=%d tz=%d ms=%.4f\n", key, by, bx, btz, best);
+      std::fclose(fh);
+    }
+  }
+  return COLA_OK;
+}
+
+// ---------------------------------------------------------------------------------
+// Ensembles: whole runs of many plans captured once into one hipGraph, one parallel
+// branch per member, and replayed with a single graph launch.
+// ---------------------------------------------------------------------------------
+struct cola_ensemble_s {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+  int members = 0;
+};
+
+int cola_ensemble_create(int32_t n, const cola_plan* plans, const float* const* w, const cola_particles* parts,
+                         float* const* x_out, float* const* v_out, void* const* ws, cola_ensemble* out) {
+  if (!out || n <= 0 || !plans || !w || !parts || !x_out || !v_out || !ws) return COLA_ERR_INVALID;
+  *out = nullptr;
+  for (int k = 0; k < n; ++k) {
+    COLA_TRY(check_common(plans[k], ws[k]));
+    COLA_TRY(check_particles(&parts[k]));
+    if (!w[k] || !x_out[k] || !v_out[k]) return COLA_ERR_INVALID;
+    if (plans[k]->trace) return COLA_ERR_INVALID;   // no event records inside a graph
+  }
+  hipStream_t s0 = nullptr;
+  std::vector<hipStream_t> side(n, nullptr);
+  std::vector<hipEvent_t> done(n, nullptr);
+  hipEvent_t fork = nullptr;
+  int rc = hip_status(hipStreamCreate(&s0));
+  for (int k = 0; k < n && rc == COLA_OK; ++k) {
+    rc = hip_status(hipStreamCreate(&side[k]));
+    if (rc == COLA_OK) rc = hip_status(hipEventCreateWithFlags(&done[k], hipEventDisableTiming));
+  }
+  if (rc == COLA_OK) rc = hip_status(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  hipGraph_t graph = nullptr;
+  bool capturing = false;
+  if (rc == COLA_OK) {
+    rc = hip_status(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
+    capturing = rc == COLA_OK;
+  }
+  if (rc == COLA_OK) rc = hip_status(hipEventRecord(fork, s0));
+  for (int k = 0; k < n && rc == COLA_OK; ++k) {
+    rc = hip_status(hipStreamWaitEvent(side[k], fork, 0));
+    if (rc == COLA_OK) rc = cola_run(plans[k], w[k], &parts[k], x_out[k], v_out[k], ws[k], side[k]);
+    if (rc == COLA_OK) rc = hip_status(hipEventRecord(done[k], side[k]));
+    if (rc == COLA_OK) rc = hip_status(hipStreamWaitEvent(s0, done[k], 0));
+  }
+  if (capturing) {
+    const int rc_end = hip_status(hipStreamEndCapture(s0, &graph));
+    if (rc == COLA_OK) rc = rc_end;
+  }
+  cola_ensemble e = nullptr;
+  if (rc == COLA_OK) {
+    e = new (std::nothrow) cola_ensemble_s();
+    if (!e) rc = COLA_ERR_INVALID;
+  }
+  if (rc == COLA_OK) {
+    e->graph = graph;
+    e->members = n;
+    (void)hipGetDevice(&e->device);
+    rc = hip_status(hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0));
+  }
+  for (int k = 0; k < n; ++k) {
+    if (done[k]) (void)hipEventDestroy(done[k]);
+    if (side[k]) (void)hipStreamDestroy(side[k]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (s0) (void)hipStreamDestroy(s0);
+  if (rc != COLA_OK) {
+    if (e) {
+      if (e->exec) (void)hipGraphExecDestroy(e->exec);
+      delete e;
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  *out = e;
+  return COLA_OK;
+}
+
+int cola_ensemble_launch(cola_ensemble e, void* stream) {
+  if (!e || !e->exec) return COLA_ERR_INVALID;
+  return hip_status(hipGraphLaunch(e->exec, (hipStream_t)stream));
+}
+
+int cola_ensemble_destroy(cola_ensemble e) {
+  if (!e) return COLA_OK;
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  delete e;
   return COLA_OK;
 }
 

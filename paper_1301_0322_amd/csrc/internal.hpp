@@ -95,7 +95,8 @@ struct BinBuffers {
   float* halo;       // [nbins * halo] halo faces of each tile's deposit
   long count_len;
 };
-Bins make_bins(int nm);
+// Tile depth: the largest of 8, 16, 32 (<= tz_max) dividing nm.
+Bins make_bins(int nm, int tz_max = 32);
 size_t bin_workspace_bytes(long npart, const Bins& b);
 BinBuffers carve_bins(void* base, long npart, const Bins& b);
 

@@ -674,12 +674,12 @@ __global__ __launch_bounds__(kPartThreads) void k_noise(uint64_t seed, float* __
 }
 
 // ---------------------------------------------------------------------------------
-Bins make_bins(int nm) {
+Bins make_bins(int nm, int tz_max) {
   Bins b;
   b.tx = kTX;
   b.ty = kTY;
   b.tz = 8;
-  while (b.tz < 32 && nm % (2 * b.tz) == 0) b.tz *= 2;
+  while (b.tz < tz_max && b.tz < 32 && nm % (2 * b.tz) == 0) b.tz *= 2;
   b.nbx = nm / b.tx;
   b.nby = nm / b.ty;
   b.nbz = nm / b.tz;
