@@ -114,15 +114,19 @@ def cpu_baseline(np_side: int, nm: int, box: float, seed: int) -> dict:
     table = cosmo.step_table(cfg)
     s1, s2 = lpt.lpt_from_noise(w, cfg)
     st = ocola.initial_state(s1, s2, table)
+    # COLA steps from the start of the run until about 10 s of CPU time have passed
+    steps = 0
     t0 = time.perf_counter()
-    st = ocola.step(st, 0, table, cfg)
+    while steps < cfg.n_steps and (steps == 0 or time.perf_counter() - t0 < 10.0):
+        st = ocola.step(st, steps, table, cfg)
+        steps += 1
     dt = time.perf_counter() - t0
     assert np.isfinite(st.s.sum().item())
     return {
-        "value": np_side**3 / dt, "unit": "particle-steps/s", "cores": torch.get_num_threads(),
+        "value": steps * np_side**3 / dt, "unit": "particle-steps/s", "cores": torch.get_num_threads(),
         "kind": "oracle",
-        "sample": f"one COLA step (PM force, kick, drift) of the {np_side}^3/{nm}^3 workload in FP64 "
-                  f"torch-CPU, after oracle 2LPT ICs from the same Philox seed (ICs untimed); "
+        "sample": f"the first {steps} COLA steps (PM force, kick, drift) of the {np_side}^3/{nm}^3 workload "
+                  f"in FP64 torch-CPU, after oracle 2LPT ICs from the same Philox seed (ICs untimed); "
                   f"{dt:.1f} s",
     }
 
@@ -228,6 +232,8 @@ def main() -> int:
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy 256 MiB device to device once (a known-size kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -334,6 +340,14 @@ def main() -> int:
     if not args.no_adjoint:
         out["adjoint"] = bench_adjoint(stream)
         torch.cuda.empty_cache()
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(np_side, nm, box, seed)
     print(json.dumps(out), flush=True)
