@@ -213,6 +213,38 @@ __device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom
   return (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
 }
 
+// Copies NF mesh fields over the tile's (8+1) x (8+1) x (TZ+1) extent (periodic
+// wrap) into LDS, field c at tile + c * EXT.  Every load of a lane is issued before
+// its first LDS write, so a block has all of its tile reads in flight at once.
+template <int TZ, int NF>
+__device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const float* const* f, float* tile) {
+  using D = TileDims<TZ>;
+  constexpr int IT = (D::EXT + kPartThreads - 1) / kPartThreads;
+  float v[NF][IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int i = threadIdx.x + k * kPartThreads;
+    const int ii = i < D::EXT ? i : D::EXT - 1;
+    const int z = ii % D::EZ, r = ii / D::EZ;
+    const int y = r % D::EY, x = r / D::EY;
+    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
+    gx -= (gx >= nm) ? nm : 0;
+    gy -= (gy >= nm) ? nm : 0;
+    gz -= (gz >= nm) ? nm : 0;
+    const long gi = ((long)gx * nm + gy) * nm + gz;
+#pragma unroll
+    for (int c = 0; c < NF; ++c) v[c][k] = f[c][gi];
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int i = threadIdx.x + k * kPartThreads;
+    if (i < D::EXT) {
+#pragma unroll
+      for (int c = 0; c < NF; ++c) tile[c * D::EXT + i] = v[c][k];
+    }
+  }
+}
+
 template <int TZ>
 __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
                                                                 const int* __restrict__ idx,
@@ -326,18 +358,9 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
   __shared__ float tile[3 * D::EXT];
   TileGeom t;
   if (!tile_geom<TZ>(bins, t)) return;
-  const int nm = lat.nm;
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) {
-    const int z = i % D::EZ, r = i / D::EZ;
-    const int y = r % D::EY, x = r / D::EY;
-    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
-    gx -= (gx >= nm) ? nm : 0;
-    gy -= (gy >= nm) ? nm : 0;
-    gz -= (gz >= nm) ? nm : 0;
-    const long gi = ((long)gx * nm + gy) * nm + gz;
-    tile[i] = g.g0[gi];
-    tile[D::EXT + i] = g.g1[gi];
-    tile[2 * D::EXT + i] = g.g2[gi];
+  {
+    const float* f[3] = {g.g0, g.g1, g.g2};
+    stage_fields<TZ, 3>(t, lat.nm, f, tile);
   }
   __syncthreads();
   const long n = lat.npart;
@@ -415,22 +438,13 @@ __global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins 
   __shared__ float tile[4 * D::EXT];
   TileGeom t;
   if (!tile_geom<TZ>(bins, t)) return;
-  const int nm = lat.nm;
   const bool with_g = ga.g0 != nullptr;
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) {
-    const int z = i % D::EZ, r = i / D::EZ;
-    const int y = r % D::EY, x = r / D::EY;
-    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
-    gx -= (gx >= nm) ? nm : 0;
-    gy -= (gy >= nm) ? nm : 0;
-    gz -= (gz >= nm) ? nm : 0;
-    const long gi = ((long)gx * nm + gy) * nm + gz;
-    tile[3 * D::EXT + i] = ga.rbar[gi];
-    if (with_g) {
-      tile[i] = ga.g0[gi];
-      tile[D::EXT + i] = ga.g1[gi];
-      tile[2 * D::EXT + i] = ga.g2[gi];
-    }
+  if (with_g) {
+    const float* f[4] = {ga.g0, ga.g1, ga.g2, ga.rbar};
+    stage_fields<TZ, 4>(t, lat.nm, f, tile);
+  } else {
+    const float* f[1] = {ga.rbar};
+    stage_fields<TZ, 1>(t, lat.nm, f, tile + 3 * D::EXT);
   }
   __syncthreads();
   const long n = lat.npart;
@@ -484,45 +498,77 @@ __global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins 
 //   gather_sorted per tile: coalesced gather + kick + drift on the sorted copy, then
 //                 counts the drifted particles into next step's tiles.
 // ---------------------------------------------------------------------------------
+// One particle's state at slot j.  A state without a lag array (the caller's
+// arrays, in Lagrangian order) has lag = j.
+struct SortedRecord {
+  unsigned lag;
+  float s[3], v[3], s1[3], s2[3];
+};
+
+__device__ __forceinline__ void load_record(const SortedState& st, long n, int j, SortedRecord& r) {
+  r.lag = st.lag ? (unsigned)st.lag[j] : (unsigned)j;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    r.s[d] = st.s[d * n + j];
+    r.v[d] = st.v[d * n + j];
+    r.s1[d] = st.s1[d * n + j];
+    r.s2[d] = st.s2[d * n + j];
+  }
+}
+
 template <int TZ>
 __global__ __launch_bounds__(kPartThreads) void k_deposit_perm(Lattice lat, Bins bins, SortedState src,
                                                                SortedState dst, const int* __restrict__ idx,
                                                                const int* __restrict__ offset, float* __restrict__ rho,
                                                                float* __restrict__ halo, float mass) {
   using D = TileDims<TZ>;
+  constexpr int U = 2;   // particles per lane per batch, so their dependent reads overlap
   __shared__ float tile[D::EXT];
   TileGeom g;
   if (!tile_geom<TZ>(bins, g)) return;
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0.f;
-  __syncthreads();
   const long n = lat.npart;
   const int beg = offset[g.bin], end = offset[g.bin + 1];
-  for (int j = beg + threadIdx.x; j < end; j += kPartThreads) {
-    const int from = idx[j];
-    const unsigned lag = src.lag ? (unsigned)src.lag[from] : (unsigned)from;
-    float sv[3];
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0.f;
+  for (int base = beg; base < end; base += U * kPartThreads) {   // block-uniform trip count
+    SortedRecord r[U];
+    bool in[U];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      sv[d] = src.s[d * n + from];
-      dst.s[d * n + j] = sv[d];
-      dst.v[d * n + j] = src.v[d * n + from];
-      dst.s1[d * n + j] = src.s1[d * n + from];
-      dst.s2[d * n + j] = src.s2[d * n + from];
+    for (int u = 0; u < U; ++u) {
+      const int j = base + u * kPartThreads + (int)threadIdx.x;
+      in[u] = j < end;
+      load_record(src, n, idx[in[u] ? j : base], r[u]);
     }
-    dst.lag[j] = (int)lag;
-    const Stencil st = stencil_of(lat, lag, sv);
-    const int lc[3] = {st.c[0] - g.lo[0], st.c[1] - g.lo[1], st.c[2] - g.lo[2]};
-    if ((unsigned)lc[0] >= (unsigned)kTX || (unsigned)lc[1] >= (unsigned)kTY || (unsigned)lc[2] >= (unsigned)TZ)
-      continue;   // cannot happen: binning used the same arithmetic
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int u = 0; u < U; ++u) {
+      if (!in[u]) continue;
+      const int j = base + u * kPartThreads + (int)threadIdx.x;
+      dst.lag[j] = (int)r[u].lag;
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        const float wab = mass * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
-        float* row = tile + ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
-        atomicAdd(row, wab * (1.f - st.f[2]));
-        atomicAdd(row + 1, wab * st.f[2]);
+      for (int d = 0; d < 3; ++d) {
+        dst.s[d * n + j] = r[u].s[d];
+        dst.v[d * n + j] = r[u].v[d];
+        dst.s1[d * n + j] = r[u].s1[d];
+        dst.s2[d * n + j] = r[u].s2[d];
       }
+    }
+    if (base == beg) __syncthreads();   // the zeroed tile is complete before the first adds
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const Stencil st = stencil_of(lat, r[u].lag, r[u].s);
+      const int lc[3] = {st.c[0] - g.lo[0], st.c[1] - g.lo[1], st.c[2] - g.lo[2]};
+      if (!in[u] || (unsigned)lc[0] >= (unsigned)kTX || (unsigned)lc[1] >= (unsigned)kTY ||
+          (unsigned)lc[2] >= (unsigned)TZ)
+        continue;   // out of the tile cannot happen: binning used the same arithmetic
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const float wab = mass * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
+          float* row = tile + ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
+          atomicAdd(row, wab * (1.f - st.f[2]));
+          atomicAdd(row + 1, wab * st.f[2]);
+        }
+    }
   }
   __syncthreads();
   const long nm = lat.nm;
@@ -551,31 +597,22 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
   __shared__ float tile[3 * D::EXT];
   TileGeom t;
   if (!tile_geom<TZ>(bins, t)) return;
-  const int nm = lat.nm;
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) {
-    const int z = i % D::EZ, r = i / D::EZ;
-    const int y = r % D::EY, x = r / D::EY;
-    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
-    gx -= (gx >= nm) ? nm : 0;
-    gy -= (gy >= nm) ? nm : 0;
-    gz -= (gz >= nm) ? nm : 0;
-    const long gi = ((long)gx * nm + gy) * nm + gz;
-    tile[i] = g.g0[gi];
-    tile[D::EXT + i] = g.g1[gi];
-    tile[2 * D::EXT + i] = g.g2[gi];
-  }
-  __syncthreads();
   const long n = lat.npart;
   const int beg = offset[t.bin], end = offset[t.bin + 1];
+  // The first batch of particle reads is issued before the force tile is staged,
+  // so both are in flight together (most tiles hold one batch or less).
+  SortedRecord r;
+  if (beg < end) load_record(st_, n, min(beg + (int)threadIdx.x, end - 1), r);
+  {
+    const float* f[3] = {g.g0, g.g1, g.g2};
+    stage_fields<TZ, 3>(t, lat.nm, f, tile);
+  }
+  __syncthreads();
   for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
     const int j = base + threadIdx.x;
     const bool in = j < end;
-    const int jj = in ? j : base;
-    const unsigned lag = (unsigned)st_.lag[jj];
-    float sv[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) sv[d] = st_.s[d * n + jj];
-    const Stencil sc = stencil_of(lat, lag, sv);
+    if (base != beg) load_record(st_, n, in ? j : base, r);
+    const Stencil sc = stencil_of(lat, r.lag, r.s);
     const int lc[3] = {sc.c[0] - t.lo[0], sc.c[1] - t.lo[1], sc.c[2] - t.lo[2]};
     const bool act =
         in && (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
@@ -592,26 +629,25 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
           for (int d = 0; d < 3; ++d) f[d] += w0 * tile[d * D::EXT + o] + w1 * tile[d * D::EXT + o + 1];
         }
     }
-    float snew[3] = {sv[0], sv[1], sv[2]};
+    float snew[3] = {r.s[0], r.s[1], r.s[2]};
     if (act) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        const float a1 = st_.s1[d * n + j];
-        const float a2 = st_.s2[d * n + j];
-        float v = st_.v[d * n + j];
-        v += k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
+        const float a1 = r.s1[d], a2 = r.s2[d];
+        const float v = r.v[d] + k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
         if constexpr (MODE == kGatherKickDrift) {
-          snew[d] = sv[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
+          snew[d] = r.s[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
           st_.v[d * n + j] = v;
           st_.s[d * n + j] = snew[d];
         } else {
           // finish: state back to Lagrangian order, positions and full velocities out
+          const unsigned lag = r.lag;
           g.v[d * n + lag] = v;
-          g.s[d * n + lag] = sv[d];
+          g.s[d * n + lag] = r.s[d];
           g.out_b[d * n + lag] = v + k.td1 * a1 + k.td2 * a2;
           int li[3];
           lag_index(lat, lag, li);
-          float x = (float)li[d] * (k.box / (float)lat.np) + sv[d];
+          float x = (float)li[d] * (k.box / (float)lat.np) + r.s[d];
           x = x - k.box * floorf(x / k.box);
           if (x >= k.box) x -= k.box;
           g.out_a[d * n + lag] = x;
@@ -620,7 +656,7 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
     }
     if constexpr (MODE == kGatherKickDrift) {
       int bin = 0;
-      if (act) bin = bin_of<TZ>(bins, stencil_of(lat, lag, snew).c);
+      if (act) bin = bin_of<TZ>(bins, stencil_of(lat, r.lag, snew).c);
       const int rank = wave_rank(act, bin, count_next);
       if (act) key_rank_next[j] = make_int2(bin, rank);
     }
