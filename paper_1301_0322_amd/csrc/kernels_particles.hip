@@ -63,6 +63,21 @@ struct TileDims {
   static constexpr int HALO = FX + FY + FZ;
 };
 
+// Deposit accumulators.  A tile sums its CIC contributions in LDS either as FP32
+// (float atomics) or as 64-bit fixed point with 32 fraction bits (integer atomics).
+// Integer adds are exact and associative, so the fixed-point sum does not depend on
+// the order of the adds; each contribution is its FP32 value rounded to 2^-32, and
+// the tile value is rounded to FP32 once.  It is also the faster form on gfx950,
+// whose LDS integer atomics run far ahead of its LDS float atomics.  The range is
+// enough for any supported size: a cell holds at most the total mass nm^3 <= 2^30.
+constexpr float kFixScale = 4294967296.f;   // 2^32
+__device__ __forceinline__ void tile_add(float* p, float x) { atomicAdd(p, x); }
+__device__ __forceinline__ void tile_add(unsigned long long* p, float x) {
+  atomicAdd(p, (unsigned long long)__float2ll_rn(x * kFixScale));
+}
+__device__ __forceinline__ float tile_value(float v) { return v; }
+__device__ __forceinline__ float tile_value(unsigned long long v) { return (float)(long long)v * (1.f / kFixScale); }
+
 // Base cell (wrapped) and CIC fraction along one axis.
 __device__ __forceinline__ int base_cell(int lag, int ratio, float s, float inv_dx, int nm, float& frac) {
   const float t = fmaf(s, inv_dx, -0.5f);
@@ -245,17 +260,42 @@ __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const fl
   }
 }
 
-template <int TZ>
+// Writes a deposited tile: core cells to rho (plain stores), the three +1 faces
+// to the tile's slot of the halo side buffer.
+template <int TZ, class ACC>
+__device__ __forceinline__ void write_tile(const Lattice& lat, const TileGeom& g, const ACC* tile,
+                                           float* __restrict__ rho, float* __restrict__ halo) {
+  using D = TileDims<TZ>;
+  const long nm = lat.nm;
+  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
+    const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
+    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile_value(tile[(x * D::EY + y) * D::EZ + z]);
+  }
+  float* h = halo + (long)g.bin * D::HALO;
+  for (int i = threadIdx.x; i < D::FX; i += kPartThreads) h[i] = tile_value(tile[kTX * D::EY * D::EZ + i]);
+  for (int i = threadIdx.x; i < D::FY; i += kPartThreads) {
+    const int x = i / D::EZ, z = i % D::EZ;
+    h[D::FX + i] = tile_value(tile[(x * D::EY + kTY) * D::EZ + z]);
+  }
+  for (int i = threadIdx.x; i < D::FZ; i += kPartThreads) {
+    const int x = i / kTY, y = i % kTY;
+    h[D::FX + D::FY + i] = tile_value(tile[(x * D::EY + y) * D::EZ + TZ]);
+  }
+}
+
+// ACC = unsigned long long: fixed-point sums (mass deposits); float: FP32 atomics
+// (weighted deposits, whose weights have no bounded scale).
+template <int TZ, class ACC>
 __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
                                                                 const int* __restrict__ idx,
                                                                 const int* __restrict__ offset, float* __restrict__ rho,
                                                                 float* __restrict__ halo, float mass,
                                                                 const float* __restrict__ weight) {
   using D = TileDims<TZ>;
-  __shared__ float tile[D::EXT];
+  __shared__ ACC tile[D::EXT];
   TileGeom g;
   if (!tile_geom<TZ>(bins, g)) return;
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0.f;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0;
   __syncthreads();
   const int beg = offset[g.bin], end = offset[g.bin + 1];
   // two particles per lane per iteration so their dependent loads overlap
@@ -277,28 +317,14 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bin
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const float wab = mw * (a ? fr[u][0] : 1.f - fr[u][0]) * (b ? fr[u][1] : 1.f - fr[u][1]);
-          float* row = tile + ((lc[u][0] + a) * D::EY + lc[u][1] + b) * D::EZ + lc[u][2];
-          atomicAdd(row, wab * (1.f - fr[u][2]));
-          atomicAdd(row + 1, wab * fr[u][2]);
+          ACC* row = tile + ((lc[u][0] + a) * D::EY + lc[u][1] + b) * D::EZ + lc[u][2];
+          tile_add(row, wab * (1.f - fr[u][2]));
+          tile_add(row + 1, wab * fr[u][2]);
         }
     }
   }
   __syncthreads();
-  const long nm = lat.nm;
-  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
-    const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
-    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile[(x * D::EY + y) * D::EZ + z];
-  }
-  float* h = halo + (long)g.bin * D::HALO;
-  for (int i = threadIdx.x; i < D::FX; i += kPartThreads) h[i] = tile[kTX * D::EY * D::EZ + i];
-  for (int i = threadIdx.x; i < D::FY; i += kPartThreads) {
-    const int x = i / D::EZ, z = i % D::EZ;
-    h[D::FX + i] = tile[(x * D::EY + kTY) * D::EZ + z];
-  }
-  for (int i = threadIdx.x; i < D::FZ; i += kPartThreads) {
-    const int x = i / kTY, y = i % kTY;
-    h[D::FX + D::FY + i] = tile[(x * D::EY + y) * D::EZ + TZ];
-  }
+  write_tile<TZ>(lat, g, tile, rho, halo);
 }
 
 // Adds the lower neighbours' halo faces onto the tile's cells with a zero local
@@ -523,12 +549,12 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_perm(Lattice lat, Bins
                                                                float* __restrict__ halo, float mass) {
   using D = TileDims<TZ>;
   constexpr int U = 2;   // particles per lane per batch, so their dependent reads overlap
-  __shared__ float tile[D::EXT];
+  __shared__ unsigned long long tile[D::EXT];   // fixed-point sums
   TileGeom g;
   if (!tile_geom<TZ>(bins, g)) return;
   const long n = lat.npart;
   const int beg = offset[g.bin], end = offset[g.bin + 1];
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0.f;
+  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0;
   for (int base = beg; base < end; base += U * kPartThreads) {   // block-uniform trip count
     SortedRecord r[U];
     bool in[U];
@@ -564,28 +590,14 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_perm(Lattice lat, Bins
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           const float wab = mass * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
-          float* row = tile + ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
-          atomicAdd(row, wab * (1.f - st.f[2]));
-          atomicAdd(row + 1, wab * st.f[2]);
+          unsigned long long* row = tile + ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
+          tile_add(row, wab * (1.f - st.f[2]));
+          tile_add(row + 1, wab * st.f[2]);
         }
     }
   }
   __syncthreads();
-  const long nm = lat.nm;
-  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
-    const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
-    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile[(x * D::EY + y) * D::EZ + z];
-  }
-  float* h = halo + (long)g.bin * D::HALO;
-  for (int i = threadIdx.x; i < D::FX; i += kPartThreads) h[i] = tile[kTX * D::EY * D::EZ + i];
-  for (int i = threadIdx.x; i < D::FY; i += kPartThreads) {
-    const int x = i / D::EZ, z = i % D::EZ;
-    h[D::FX + i] = tile[(x * D::EY + kTY) * D::EZ + z];
-  }
-  for (int i = threadIdx.x; i < D::FZ; i += kPartThreads) {
-    const int x = i / kTY, y = i % kTY;
-    h[D::FX + D::FY + i] = tile[(x * D::EY + y) * D::EZ + TZ];
-  }
+  write_tile<TZ>(lat, g, tile, rho, halo);
 }
 
 template <int TZ, int MODE>
@@ -791,8 +803,13 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
                           hipStream_t st, const float* weight) {
-  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_tiles<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
-                                            lat, b, s, bb.idx, bb.offset, rho, bb.halo, mass, weight));
+  if (weight)
+    COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float>), dim3(tile_blocks(b)), dim3(kPartThreads),
+                                              0, st, lat, b, s, bb.idx, bb.offset, rho, bb.halo, mass, weight))
+  else
+    COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long>), dim3(tile_blocks(b)),
+                                              dim3(kPartThreads), 0, st, lat, b, s, bb.idx, bb.offset, rho, bb.halo,
+                                              mass, weight))
   return hipGetLastError();
 }
 
