@@ -1,14 +1,5 @@
-// Device-side FFT building blocks for gfx950: in-register radix-2/3/4/8 DFTs and
-// Stockham autosort stages on a tile held in LDS.
-//
-// A tile holds B independent transforms of length L.  Element m of transform b
-// lives at lds[m * ES + b * BS].  JFAST selects the thread mapping: true makes
-// consecutive lanes walk along m (row tiles, ES = 1), false makes them walk along b
-// (column tiles, BS = 1); either way consecutive lanes touch consecutive LDS words,
-// so stage reads and writes are free of bank conflicts.
-//
-// Twiddles come from a table of exp(-2 pi i m / (L * TWS)) for m < L * TWS, rounded
-// from FP64 on the host; a stage needs W_L^e = table[e * TWS].
+// Device-side FFT building blocks for gfx950: complex arithmetic and the in-register
+// radix-2/3/4/8 DFTs that the register FFT (fft_pencil.hpp) is built from.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,72 +82,5 @@ __device__ __forceinline__ void dft(float2* x) {
   else dft8<S>(x);
 }
 
-// Radix chosen for the remaining length M: all factors 3 first, then 8s, ending
-// 4 x 4 rather than 8 x 2.
-constexpr int pick_radix(int m) {
-  return (m % 3 == 0) ? 3 : (m == 16) ? 4 : (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : 2;
-}
-
-constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
-
-// One Stockham stage: sub-transforms of length NS are combined R at a time.
-template <int L, int R, int NS, int B, int T, int ES, int BS, bool JFAST, int S, int TWS>
-__device__ __forceinline__ void fft_stage(float2* lds, const float2* tw) {
-  constexpr int NBF = (L / R) * B;
-  constexpr int PER = ceil_div(NBF, T);
-  constexpr int STR = L / R;
-  const int tid = threadIdx.x;
-  float2 v[PER][R];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int bf = tid + i * T;
-    if (NBF % T == 0 || bf < NBF) {
-      const int j = JFAST ? (bf % STR) : (bf / B);
-      const int b = JFAST ? (bf / STR) : (bf % B);
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = lds[(j + r * STR) * ES + b * BS];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int bf = tid + i * T;
-    if (NBF % T == 0 || bf < NBF) {
-      const int j = JFAST ? (bf % STR) : (bf / B);
-      const int b = JFAST ? (bf / STR) : (bf % B);
-      const int k = j % NS;
-      if constexpr (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[(r * k * (L / (NS * R))) * TWS];
-          if constexpr (S > 0) w.y = -w.y;
-          v[i][r] = c_mul(v[i][r], w);
-        }
-      }
-      dft<R, S>(v[i]);
-      const int base = (j / NS) * NS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) lds[(base + r * NS) * ES + b * BS] = v[i][r];
-    }
-  }
-  __syncthreads();
-}
-
-template <int L, int NS, int B, int T, int ES, int BS, bool JFAST, int S, int TWS>
-__device__ __forceinline__ void fft_stages(float2* lds, const float2* tw) {
-  if constexpr (NS < L) {
-    constexpr int R = pick_radix(L / NS);
-    fft_stage<L, R, NS, B, T, ES, BS, JFAST, S, TWS>(lds, tw);
-    fft_stages<L, NS * R, B, T, ES, BS, JFAST, S, TWS>(lds, tw);
-  }
-}
-
-// Unnormalised length-L DFT of every transform in the tile, in place.
-// S = -1: sum x_n exp(-2 pi i n k / L); S = +1: the conjugate kernel.
-// The caller synchronises before (data in LDS) and the routine ends synchronised.
-template <int L, int B, int T, int ES, int BS, bool JFAST, int S, int TWS>
-__device__ __forceinline__ void fft_tile(float2* lds, const float2* tw) {
-  fft_stages<L, 1, B, T, ES, BS, JFAST, S, TWS>(lds, tw);
-}
 
 }  // namespace cola

@@ -63,6 +63,7 @@ hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, 
                       hipStream_t st);
 // x pass with the k-space multiplier: forward x transform of `in`, multiply, inverse
 // x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row.
+// kMulGrad requires nout = 3, kMulLpt1 1..9.
 hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m,
                        const float2* tw, int width, hipStream_t st);
 // Whether `width` columns per tile is a valid strided-pass shape for length n.

@@ -11,40 +11,44 @@
 //   y / x       strided column FFTs over tiles of B contiguous kz columns
 //   x multiply  forward x FFT, multiplier, inverse x FFT into several outputs
 //   z inverse   rows of n/2 complex -> n reals, with fused epilogues
-#include "fft_device.hpp"
+// Every pass is a tile of the two-level register FFT (fft_pencil.hpp): data moves
+// between HBM and registers directly, with one LDS exchange per transform.
+#include "fft_pencil.hpp"
 #include "internal.hpp"
 
 namespace cola {
 
-constexpr int kThreads = 256;
-
-// ---------------------------------------------------------------------------------
-// Tile shapes per transform length.
-// ---------------------------------------------------------------------------------
 constexpr int pow2_factor(int v) { return (v & (-v)); }
-constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
 constexpr int min_i(int a, int b) { return a < b ? a : b; }
-constexpr int max_i(int a, int b) { return a > b ? a : b; }
 
-// Rows per block of the z passes: a 32 KB LDS tile of n/2 complex rows.
-template <int N>
-constexpr int z_rows() { return min_i(64, floor_pow2(4096 / (N / 2))); }
-// Rows per block of the Hessian z pass (keeps several fields in registers).
-template <int N>
-constexpr int zh_rows() { return min_i(64, floor_pow2(1024 / (N / 2))); }
-// Columns per block of the strided passes: 16 (128-byte segments) while the tile
-// stays within 64 KB, limited to a power of two dividing n/2.
-template <int N>
-constexpr int col_width() {
-  return min_i(pow2_factor(N / 2), min_i(16, max_i(2, floor_pow2(8192 / N))));
+// Rows per block of the z passes: a power of two with at most 256 threads and an LDS
+// exchange of at most 36 KB.
+template <int M>
+constexpr int z_rows() {
+  constexpr int r2 = pencil_r2(M), r1 = M / r2;
+  constexpr int per_row = pmax(r2 * (r1 + 1), r1 * (r2 + 1));
+  int rows = 1;
+  while (2 * rows * r1 <= 256 && 2 * rows * per_row <= 4608) rows *= 2;
+  return rows;
 }
+template <int N>
+using ZPencil = Pencil<N / 2, z_rows<N / 2>(), true>;
 
-// Threads per block of the strided passes: 512 for tiles of >= 8192 elements so
-// each lane holds at most 16 complex values.
-constexpr int col_threads_for(int n, int b) { return n * b >= 8192 ? 512 : 256; }
-// A column width is usable when it divides n/2 and the tile fits in 64 KB.
+// Rows per block of the Hessian z pass (two accumulators stay in registers): at most
+// 128 threads, a power of two so it divides the row count.
+constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
+template <int N>
+using ZHPencil = Pencil<N / 2, floor_pow2(min_i(z_rows<N / 2>(), pmax(1, 128 / (N / 2 / pencil_r2(N / 2))))), true>;
+
+// A column width is usable when it divides n/2, the LDS exchange stays within 64 KB and
+// the block within 1024 threads.
 template <int N, int B>
-constexpr bool col_ok() { return B >= 2 && B <= pow2_factor(N / 2) && N * B <= 8192; }
+constexpr bool col_ok() {
+  return B >= 2 && B <= pow2_factor(N / 2) && N * B <= 8192 && B * (N / pencil_r2(N)) <= 1024;
+}
+constexpr int col_width_default(int n) {
+  return (n * 16 <= 8192 && pow2_factor(n / 2) >= 16) ? 16 : (pow2_factor(n / 2) >= 8 && n * 8 <= 8192) ? 8 : 4;
+}
 
 __device__ __forceinline__ int pick_comp(int c, int nx, int ny, int nz) {
   return c == 0 ? nx : (c == 1 ? ny : nz);
@@ -60,36 +64,39 @@ __device__ __forceinline__ void load_twiddles(float2* stw, const float2* __restr
 // ---------------------------------------------------------------------------------
 // z forward: real rows -> half complex rows.
 // X[k] = (Z[k] + conj Z[M-k]) / 2 - i W^k (Z[k] - conj Z[M-k]) / 2, W = exp(-2 pi i / N),
-// where Z is the length-M = N/2 DFT of z[m] = x[2m] + i x[2m+1].
+// where Z is the length-M = N/2 DFT of z[m] = x[2m] + i x[2m+1].  Z[M-k] sits in the
+// partner lane of the same wave (Pencil::partner).
 // ---------------------------------------------------------------------------------
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_zfwd(const float* in, float2* out, const float2* __restrict__ tw) {
+__global__ __launch_bounds__(ZPencil<N>::T) void k_zfwd(const float* in, float2* out, const float2* __restrict__ tw) {
+  using P = ZPencil<N>;
   constexpr int M = N / 2;
-  constexpr int BR = z_rows<N>();
-  __shared__ __align__(16) float2 tile[BR * M];
+  __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
+  const long row0 = (long)blockIdx.x * P::NT;
+  float2 a[P::R2];
+  P::load_a(a, reinterpret_cast<const float2*>(in) + row0 * M, M);
   load_twiddles(stw, tw, N);
-  const long row0 = (long)blockIdx.x * BR;
-  const float4* src = reinterpret_cast<const float4*>(in + row0 * N);
-  for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) reinterpret_cast<float4*>(tile)[idx] = src[idx];
   __syncthreads();
-  fft_tile<M, BR, kThreads, 1, M, true, -1, 2>(tile, stw);
-  // X[k] and X[M-k] both come from the pair (Z[k], Z[M-k]).
-  constexpr int Q = M / 2 + 1;
-  for (int idx = threadIdx.x; idx < BR * Q; idx += kThreads) {
-    const int b = idx / Q, k = idx % Q;
-    float2* dst = out + (row0 + b) * M;
-    const float2 zk = tile[b * M + k];
-    const float2 zm = tile[b * M + ((M - k) % M)];
-    const float2 a = c_scale(c_add(zk, c_conj(zm)), 0.5f);
-    const float2 d = c_scale(c_sub(zk, c_conj(zm)), 0.5f);
-    dst[k] = c_add(a, mul_si<-1>(c_mul(stw[k], d)));
-    if (k != 0 && k != M - k) {
-      const float2 a2 = c_scale(c_add(zm, c_conj(zk)), 0.5f);
-      const float2 d2 = c_scale(c_sub(zm, c_conj(zk)), 0.5f);
-      dst[M - k] = c_add(a2, mul_si<-1>(c_mul(stw[M - k], d2)));
+  float2 q[P::UB][P::R1];
+  P::template fwd_like<-1, 2>(a, q, ex, stw);
+#pragma unroll
+  for (int u = 0; u < P::UB; ++u) {
+    int b, j2;
+    const bool ok = P::b_unit(u, b, j2);
+    float2 zm[P::R1];
+    P::partner(q, u, zm);
+    if (!ok) continue;
+#pragma unroll
+    for (int j1 = 0; j1 < P::R1; ++j1) {
+      const int k = j2 + P::R2 * j1;
+      const float2 zk = q[u][j1];
+      const float2 s = c_scale(c_add(zk, c_conj(zm[j1])), 0.5f);
+      const float2 d = c_scale(c_sub(zk, c_conj(zm[j1])), 0.5f);
+      q[u][j1] = c_add(s, mul_si<-1>(c_mul(stw[k], d)));
     }
   }
+  P::store_b(q, out + row0 * M, M);
 }
 
 // ---------------------------------------------------------------------------------
@@ -97,215 +104,203 @@ __global__ __launch_bounds__(kThreads) void k_zfwd(const float* in, float2* out,
 // Z'[k] = (X[k] + conj X[M-k]) + i W^-k (X[k] - conj X[M-k]) with X[M] = 0;
 // its unnormalised inverse length-M DFT is x[2m] + i x[2m+1].
 // ---------------------------------------------------------------------------------
-// Requires stw to be visible to the whole block on entry (callers synchronise
-// after loading it).
-template <int N, int BR>
-__device__ __forceinline__ void zinv_tile(float2* tile, const float2* stw, const float2* src) {
-  constexpr int M = N / 2;
-  constexpr int Q = M / 2 + 1;   // work items per row: k = 0..M/2, each also producing M - k
-  // Each item loads X[k] and X[M-k] straight from memory and writes Z'[k], Z'[M-k].
-  for (int idx = threadIdx.x; idx < BR * Q; idx += kThreads) {
-    const int b = idx / Q, k = idx % Q;
-    const float2* row = src + b * M;
-    float2* out = tile + b * M;
-    const float2 xk = row[k];
-    if (k == 0) {
-      out[0] = c_add(xk, mul_si<1>(xk));                         // X[M] = 0
-    } else {
-      const float2 xm = row[M - k];
-      out[k] = c_add(c_add(xk, c_conj(xm)), mul_si<1>(c_mul(c_conj(stw[k]), c_sub(xk, c_conj(xm)))));
-      if (k != M - k)
-        out[M - k] = c_add(c_add(xm, c_conj(xk)), mul_si<1>(c_mul(c_conj(stw[M - k]), c_sub(xm, c_conj(xk)))));
+// Pre-processing of loaded B-layout registers, then the inverse half-length transform.
+template <class P, int N>
+__device__ __forceinline__ void zinv_regs(float2 (&q)[P::UB][P::R1], float2 (&a)[P::R2], float2* ex,
+                                          const float2* stw) {
+#pragma unroll
+  for (int u = 0; u < P::UB; ++u) {
+    int b, j2;
+    const bool ok = P::b_unit(u, b, j2);
+    float2 xm[P::R1];
+    P::partner(q, u, xm);
+    if (!ok) continue;
+#pragma unroll
+    for (int j1 = 0; j1 < P::R1; ++j1) {
+      const int k = j2 + P::R2 * j1;
+      const float2 xk = q[u][j1];
+      const float2 m = (j1 == 0 && j2 == 0) ? make_float2(0.f, 0.f) : xm[j1];
+      q[u][j1] = c_add(c_add(xk, c_conj(m)), mul_si<1>(c_mul(c_conj(stw[k]), c_sub(xk, c_conj(m)))));
     }
   }
-  __syncthreads();
-  fft_tile<M, BR, kThreads, 1, M, true, 1, 2>(tile, stw);
+  P::template inv_like<1, 2>(q, a, ex, stw);
 }
 
 template <int N, int EPI>
-__global__ __launch_bounds__(kThreads) void k_zinv(FieldPtrs in, FieldPtrs out, const float2* __restrict__ tw,
-                                                   EpiArgs e) {
+__global__ __launch_bounds__(ZPencil<N>::T) void k_zinv(FieldPtrs in, FieldPtrs out, const float2* __restrict__ tw,
+                                                         EpiArgs e) {
+  using P = ZPencil<N>;
   constexpr int M = N / 2;
-  constexpr int BR = z_rows<N>();
-  __shared__ __align__(16) float2 tile[BR * M];
+  __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
-  load_twiddles(stw, tw, N);
-  __syncthreads();   // zinv_tile reads the twiddles before its first barrier
   const int f = blockIdx.y;
-  const long row0 = (long)blockIdx.x * BR;
-  zinv_tile<N, BR>(tile, stw, in.p[f] + row0 * M);
-  float4* dst = reinterpret_cast<float4*>(reinterpret_cast<float*>(out.p[f]) + row0 * N);
+  const long row0 = (long)blockIdx.x * P::NT;
+  float2 q[P::UB][P::R1];
+  P::load_b(q, in.p[f] + row0 * M, M);
+  load_twiddles(stw, tw, N);
+  __syncthreads();
+  float2 a[P::R2];
+  zinv_regs<P, N>(q, a, ex, stw);
+#pragma unroll
+  for (int i = 0; i < P::R2; ++i) a[i] = c_scale(a[i], e.scale);
+  float2* dst = out.p[f] + row0 * M;
   if constexpr (EPI == kEpiStore) {
-    for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) {
-      const float4 ab = reinterpret_cast<const float4*>(tile)[idx];
-      dst[idx] = make_float4(ab.x * e.scale, ab.y * e.scale, ab.z * e.scale, ab.w * e.scale);
-    }
+    P::store_a(a, dst, M);
   } else {
+    // s2 = x; s = d1 s1 + d2 s2; v = v1 s1 + v2 s2 (component f)
     const long off = f * e.comp_stride + row0 * N;
-    const float4* s1 = reinterpret_cast<const float4*>(e.s1 + off);
-    float4* s = reinterpret_cast<float4*>(e.s + off);
-    float4* v = reinterpret_cast<float4*>(e.v + off);
-    for (int idx = threadIdx.x; idx < BR * M / 2; idx += kThreads) {
-      const float4 ab = reinterpret_cast<const float4*>(tile)[idx];
-      const float4 x2 = make_float4(ab.x * e.scale, ab.y * e.scale, ab.z * e.scale, ab.w * e.scale);
-      const float4 x1 = s1[idx];
-      dst[idx] = x2;
-      s[idx] = make_float4(e.d1 * x1.x + e.d2 * x2.x, e.d1 * x1.y + e.d2 * x2.y,
-                           e.d1 * x1.z + e.d2 * x2.z, e.d1 * x1.w + e.d2 * x2.w);
-      v[idx] = make_float4(e.v1 * x1.x + e.v2 * x2.x, e.v1 * x1.y + e.v2 * x2.y,
-                           e.v1 * x1.z + e.v2 * x2.z, e.v1 * x1.w + e.v2 * x2.w);
+    const float2* s1 = reinterpret_cast<const float2*>(e.s1 + off);
+    float2 x1[P::R2], sv[P::R2], vv[P::R2];
+    P::load_a(x1, s1, M);
+#pragma unroll
+    for (int i = 0; i < P::R2; ++i) {
+      sv[i] = make_float2(e.d1 * x1[i].x + e.d2 * a[i].x, e.d1 * x1[i].y + e.d2 * a[i].y);
+      vv[i] = make_float2(e.v1 * x1[i].x + e.v2 * a[i].x, e.v1 * x1[i].y + e.v2 * a[i].y);
     }
+    P::store_a(a, dst, M);
+    P::store_a(sv, reinterpret_cast<float2*>(e.s + off), M);
+    P::store_a(vv, reinterpret_cast<float2*>(e.v + off), M);
   }
 }
 
-// Six Hessian fields -> S, one field at a time through the same LDS tile.
+// Six Hessian fields -> S, accumulated in registers one field at a time.
 template <int N>
-__global__ __launch_bounds__(kThreads) void k_zinv_hess(FieldPtrs in, float* out, const float2* __restrict__ tw,
-                                                        float scale) {
+__global__ __launch_bounds__(ZHPencil<N>::T) void k_zinv_hess(FieldPtrs in, float* out, const float2* __restrict__ tw,
+                                                              float scale) {
+  using P = ZHPencil<N>;
   constexpr int M = N / 2;
-  constexpr int BR = zh_rows<N>();
-  constexpr int PER = ceil_div(BR * M, kThreads);
-  __shared__ __align__(16) float2 tile[BR * M];
+  __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
-  __syncthreads();   // zinv_tile reads the twiddles before its first barrier
-  const long row0 = (long)blockIdx.x * BR;
-  float2 dg[3][PER];
-  float2 acc[PER];
-#pragma unroll
-  for (int i = 0; i < PER; ++i) acc[i] = make_float2(0.f, 0.f);
-#pragma unroll
+  const long row0 = (long)blockIdx.x * P::NT;
+  // S = xx yy + zz (xx + yy) - xy^2 - yz^2 - zx^2, accumulated as the fields arrive:
+  // sum holds xx (+ yy), acc the products.
+  float2 sum[P::R2], acc[P::R2];
+#pragma unroll 1
   for (int f = 0; f < 6; ++f) {
-    zinv_tile<N, BR>(tile, stw, in.p[f] + row0 * M);
+    float2 q[P::UB][P::R1];
+    P::load_b(q, in.p[f] + row0 * M, M);
+    __syncthreads();   // twiddles visible / previous exchange consumed
+    float2 a[P::R2];
+    zinv_regs<P, N>(q, a, ex, stw);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = threadIdx.x + i * kThreads;
-      if ((BR * M) % kThreads == 0 || idx < BR * M) {
-        const float2 t = c_scale(tile[idx], scale);
-        if (f < 3) {
-          dg[f][i] = t;
-        } else {
-          acc[i].x -= t.x * t.x;
-          acc[i].y -= t.y * t.y;
-        }
+    for (int i = 0; i < P::R2; ++i) {
+      const float2 t = c_scale(a[i], scale);
+      if (f == 0) {
+        sum[i] = t;
+        acc[i] = make_float2(0.f, 0.f);
+      } else if (f < 3) {
+        acc[i].x += sum[i].x * t.x;
+        acc[i].y += sum[i].y * t.y;
+        sum[i] = c_add(sum[i], t);
+      } else {
+        acc[i].x -= t.x * t.x;
+        acc[i].y -= t.y * t.y;
       }
     }
-    __syncthreads();
   }
-  float2* dst = reinterpret_cast<float2*>(out + row0 * N);
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * kThreads;
-    if ((BR * M) % kThreads == 0 || idx < BR * M) {
-      float2 r = acc[i];
-      r.x += dg[0][i].x * dg[1][i].x + dg[1][i].x * dg[2][i].x + dg[2][i].x * dg[0][i].x;
-      r.y += dg[0][i].y * dg[1][i].y + dg[1][i].y * dg[2][i].y + dg[2][i].y * dg[0][i].y;
-      dst[idx] = r;
-    }
-  }
+  P::store_a(acc, reinterpret_cast<float2*>(out) + row0 * M, M);
 }
 
 // ---------------------------------------------------------------------------------
 // Strided column pass: tile = n elements along inner_stride x B contiguous columns.
-// LDS layout [m][b] (b fastest): global float4 loads cover 2 columns each.
 // ---------------------------------------------------------------------------------
-template <int N, int B, int T>
-__device__ __forceinline__ void col_load(float2* tile, const float2* src, long inner_stride) {
-  for (int idx = threadIdx.x; idx < N * B / 2; idx += T) {
-    const int m = idx / (B / 2), q = idx % (B / 2);
-    reinterpret_cast<float4*>(tile)[idx] = *reinterpret_cast<const float4*>(src + m * inner_stride + 2 * q);
-  }
-}
-
-template <int N, int B, int T>
-__device__ __forceinline__ void col_store(const float2* tile, float2* dst, long inner_stride) {
-  for (int idx = threadIdx.x; idx < N * B / 2; idx += T) {
-    const int m = idx / (B / 2), q = idx % (B / 2);
-    *reinterpret_cast<float4*>(dst + m * inner_stride + 2 * q) = reinterpret_cast<const float4*>(tile)[idx];
-  }
-}
-
-template <int N, int B, int S, int T = col_threads_for(N, B)>
-__global__ __launch_bounds__(T) void k_col(FieldPtrs in, FieldPtrs out, long outer_stride, long inner_stride,
-                                           int ntiles_c, const float2* __restrict__ tw) {
-  __shared__ __align__(16) float2 tile[N * B];
+template <int N, int B, int S>
+__global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, FieldPtrs out, long outer_stride,
+                                                                long inner_stride, int ntiles_c,
+                                                                const float2* __restrict__ tw) {
+  using P = Pencil<N, B, false>;
+  __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
-  load_twiddles(stw, tw, N);
   const int f = blockIdx.y;
   const int tc = blockIdx.x % ntiles_c;
   const long o = blockIdx.x / ntiles_c;
   const long origin = o * outer_stride + (long)tc * B;
-  col_load<N, B, T>(tile, in.p[f] + origin, inner_stride);
+  float2 a[P::R2];
+  P::load_a(a, in.p[f] + origin, inner_stride);
+  load_twiddles(stw, tw, N);
   __syncthreads();
-  fft_tile<N, B, T, B, 1, false, S, 1>(tile, stw);
-  col_store<N, B, T>(tile, out.p[f] + origin, inner_stride);
+  float2 q[P::UB][P::R1];
+  P::template fwd_like<S, 1>(a, q, ex, stw);
+  P::store_b(q, out.p[f] + origin, inner_stride);
 }
 
 // ---------------------------------------------------------------------------------
 // x pass with multiplier.  Tile = n elements along x (stride n * n/2) x B kz columns
 // at fixed y.  Mode numbers: nx from the row m, ny from y, nz = kz (< n/2).
 // Modes with nx or ny equal to n/2, and the k = 0 mode, get multiplier 0.
+// The forward spectrum is held in registers, pre-scaled by the part of the multiplier
+// shared by all outputs (c / n^2, or tab[n^2]); each output then applies its own
+// factor and is inverse transformed.
 // ---------------------------------------------------------------------------------
-template <int N, int B, int MODE, int T = col_threads_for(N, B)>
-__global__ __launch_bounds__(T) void k_xmul(const float2* in, FieldPtrs out, int nout, MulArgs ma,
-                                            const float2* __restrict__ tw) {
+template <int N, int B, int MODE>
+__global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul(const float2* in, FieldPtrs out, int nout,
+                                                                 MulArgs ma, const float2* __restrict__ tw) {
+  using P = Pencil<N, B, false>;
   constexpr int H = N / 2;
   constexpr int NT = H / B;
-  constexpr int PER = ceil_div(N * B, T);
-  constexpr bool FULL = (N * B) % T == 0;
-  __shared__ __align__(16) float2 tile[N * B];
+  __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
-  load_twiddles(stw, tw, N);
   const int tc = blockIdx.x % NT;
   const int y = blockIdx.x / NT;
   const long inner = (long)N * H;
   const long origin = (long)y * H + tc * B;
-  col_load<N, B, T>(tile, in + origin, inner);
+  float2 a[P::R2];
+  P::load_a(a, in + origin, inner);
+  load_twiddles(stw, tw, N);
   __syncthreads();
-  fft_tile<N, B, T, B, 1, false, -1, 1>(tile, stw);
-  // The forward spectrum stays in registers; mode numbers are recomputed per use.
-  float2 xs[PER];
+  float2 xs[P::UB][P::R1];
+  P::template fwd_like<-1, 1>(a, xs, ex, stw);
   const int ny = (y <= H) ? y : y - N;
   const bool ny_ok = (y != H);
 #pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * T;
-    const int m = idx / B, b = idx % B;
-    const int nx = (m <= H) ? m : m - N;
+  for (int u = 0; u < P::UB; ++u) {
+    int b, j2;
+    P::b_unit(u, b, j2);
     const int nz = tc * B + b;
-    const bool keep = (FULL || idx < N * B) && ny_ok && (m != H) && (nx != 0 || ny != 0 || nz != 0);
-    xs[i] = keep ? tile[idx] : make_float2(0.f, 0.f);
-  }
-  for (int o = 0; o < nout; ++o) {
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = threadIdx.x + i * T;
-      if (!FULL && idx >= N * B) continue;
-      const int m = idx / B, b = idx % B;
+    for (int j1 = 0; j1 < P::R1; ++j1) {
+      const int m = j2 + P::R2 * j1;
       const int nx = (m <= H) ? m : m - N;
-      const int nz = tc * B + b;
-      const int nsq = max_i(1, nx * nx + ny * ny + nz * nz);
-      float2 r;
-      if constexpr (MODE == kMulGrad) {
-        const int nj = pick_comp(o, nx, ny, nz);
-        r = mul_si<1>(c_scale(xs[i], ma.c * (float)nj / (float)nsq));   // i c n_j / n^2 X
-      } else {
-        const float t = ma.tab[nsq];
-        if (o < 3) {
-          const int nj = pick_comp(o, nx, ny, nz);
-          r = mul_si<1>(c_scale(xs[i], t * (float)nj));                  // s1_j
-        } else {
-          const int na = pick_comp(hess_a(o - 3), nx, ny, nz);
-          const int nb = pick_comp(hess_b(o - 3), nx, ny, nz);
-          r = c_scale(xs[i], ma.kf * t * (float)(na * nb));              // phi_ab
-        }
-      }
-      tile[idx] = r;
+      const int nsq = nx * nx + ny * ny + nz * nz;
+      const bool keep = ny_ok && (m != H) && nsq != 0;
+      float w;
+      if constexpr (MODE == kMulGrad) w = ma.c / (float)max(nsq, 1);
+      else w = ma.tab[nsq];
+      xs[u][j1] = keep ? c_scale(xs[u][j1], w) : make_float2(0.f, 0.f);
     }
-    __syncthreads();
-    fft_tile<N, B, T, B, 1, false, 1, 1>(tile, stw);
-    col_store<N, B, T>(tile, out.p[o] + origin, inner);
+  }
+  // One output: c = factor(o) * X', inverse x transform, store.
+  auto emit = [&](int o, auto factor) {
+    float2 c[P::UB][P::R1];
+#pragma unroll
+    for (int u = 0; u < P::UB; ++u) {
+      int b, j2;
+      P::b_unit(u, b, j2);
+#pragma unroll
+      for (int j1 = 0; j1 < P::R1; ++j1) c[u][j1] = factor(xs[u][j1], b, j2 + P::R2 * j1);
+    }
+    __syncthreads();   // the previous exchange has been read
+    float2 r[P::R2];
+    P::template inv_like<1, 1>(c, r, ex, stw);
+    P::store_a(r, out.p[o] + origin, inner);
+  };
+  auto nx_of = [](int m) { return (m <= H) ? m : m - N; };
+  if constexpr (MODE == kMulGrad) {
+    // i n_j X' for j = x, y, z; n_y is uniform over the tile and n_z over a column.
+    emit(0, [&](float2 v, int, int m) { return mul_si<1>(c_scale(v, (float)nx_of(m))); });
+    emit(1, [&](float2 v, int, int) { return mul_si<1>(c_scale(v, (float)ny)); });
+    emit(2, [&](float2 v, int b, int) { return mul_si<1>(c_scale(v, (float)(tc * B + b))); });
+  } else {
+    for (int o = 0; o < nout; ++o) {
+      emit(o, [&](float2 v, int b, int m) {
+        const int nx = nx_of(m), nz = tc * B + b;
+        if (o < 3) return mul_si<1>(c_scale(v, (float)pick_comp(o, nx, ny, nz)));     // s1_j: i n_j X'
+        const int na = pick_comp(hess_a(o - 3), nx, ny, nz);
+        const int nb = pick_comp(hess_b(o - 3), nx, ny, nz);
+        return c_scale(v, ma.kf * (float)(na * nb));                                   // phi_ab: kf n_a n_b X'
+      });
+    }
   }
 }
 
@@ -314,14 +309,13 @@ __global__ __launch_bounds__(T) void k_xmul(const float2* in, FieldPtrs out, int
 // multiplied by the complex conjugate of its multiplier and accumulated; the sum is
 // inverse transformed into the single output.
 // ---------------------------------------------------------------------------------
-template <int N, int B, int MODE, int T = col_threads_for(N, B)>
-__global__ __launch_bounds__(T) void k_xmul_adj(FieldPtrs in, int nin, float2* out, MulArgs ma,
-                                                const float2* __restrict__ tw) {
+template <int N, int B, int MODE>
+__global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul_adj(FieldPtrs in, int nin, float2* out, MulArgs ma,
+                                                                     const float2* __restrict__ tw) {
+  using P = Pencil<N, B, false>;
   constexpr int H = N / 2;
   constexpr int NT = H / B;
-  constexpr int PER = ceil_div(N * B, T);
-  constexpr bool FULL = (N * B) % T == 0;
-  __shared__ __align__(16) float2 tile[N * B];
+  __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
   const int tc = blockIdx.x % NT;
@@ -330,52 +324,53 @@ __global__ __launch_bounds__(T) void k_xmul_adj(FieldPtrs in, int nin, float2* o
   const long origin = (long)y * H + tc * B;
   const int ny = (y <= H) ? y : y - N;
   const bool ny_ok = (y != H);
-  float2 acc[PER];
+  float2 acc[P::UB][P::R1];
 #pragma unroll
-  for (int i = 0; i < PER; ++i) acc[i] = make_float2(0.f, 0.f);
-  for (int f = 0; f < nin; ++f) {
-    if (f > 0) __syncthreads();
-    col_load<N, B, T>(tile, in.p[f] + origin, inner);
-    __syncthreads();
-    fft_tile<N, B, T, B, 1, false, -1, 1>(tile, stw);
+  for (int u = 0; u < P::UB; ++u)
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int idx = threadIdx.x + i * T;
-      if (!FULL && idx >= N * B) continue;
-      const int m = idx / B, b = idx % B;
-      const int nx = (m <= H) ? m : m - N;
+    for (int j1 = 0; j1 < P::R1; ++j1) acc[u][j1] = make_float2(0.f, 0.f);
+  // Adds conj(multiplier_f) * FFT_x(in_f) to acc; conj_mul(x, b, m, nsq) is the product.
+  auto absorb = [&](int f, auto conj_mul) {
+    float2 a[P::R2];
+    P::load_a(a, in.p[f] + origin, inner);
+    __syncthreads();   // twiddles visible / previous exchange consumed
+    float2 q[P::UB][P::R1];
+    P::template fwd_like<-1, 1>(a, q, ex, stw);
+#pragma unroll
+    for (int u = 0; u < P::UB; ++u) {
+      int b, j2;
+      P::b_unit(u, b, j2);
       const int nz = tc * B + b;
-      const bool keep = ny_ok && (m != H) && (nx != 0 || ny != 0 || nz != 0);
-      if (!keep) continue;
-      const int nsq = nx * nx + ny * ny + nz * nz;
-      const float2 x = tile[idx];
-      float2 r;
-      if constexpr (MODE == kMulGrad) {
-        const int nj = pick_comp(f, nx, ny, nz);
-        r = mul_si<-1>(c_scale(x, ma.c * (float)nj / (float)nsq));    // conj(i c n_j / n^2) X
-      } else {
-        const float t = ma.tab[nsq];
-        if (f < 3) {
-          const int nj = pick_comp(f, nx, ny, nz);
-          r = mul_si<-1>(c_scale(x, t * (float)nj));                     // conj(i n_j t) X
-        } else {
-          const int na = pick_comp(hess_a(f - 3), nx, ny, nz);
-          const int nb = pick_comp(hess_b(f - 3), nx, ny, nz);
-          r = c_scale(x, ma.kf * t * (float)(na * nb));                   // real multiplier
-        }
+#pragma unroll
+      for (int j1 = 0; j1 < P::R1; ++j1) {
+        const int m = j2 + P::R2 * j1;
+        const int nx = (m <= H) ? m : m - N;
+        const int nsq = nx * nx + ny * ny + nz * nz;
+        const bool keep = ny_ok && (m != H) && nsq != 0;
+        if (keep) acc[u][j1] = c_add(acc[u][j1], conj_mul(q[u][j1], nx, nz, nsq));
       }
-      acc[i] = c_add(acc[i], r);
+    }
+  };
+  if constexpr (MODE == kMulGrad) {
+    // conj(i c n_j / n^2) X
+    absorb(0, [&](float2 x, int nx, int, int nsq) { return mul_si<-1>(c_scale(x, ma.c * (float)nx / (float)nsq)); });
+    absorb(1, [&](float2 x, int, int, int nsq) { return mul_si<-1>(c_scale(x, ma.c * (float)ny / (float)nsq)); });
+    absorb(2, [&](float2 x, int, int nz, int nsq) { return mul_si<-1>(c_scale(x, ma.c * (float)nz / (float)nsq)); });
+  } else {
+    for (int f = 0; f < nin; ++f) {
+      absorb(f, [&](float2 x, int nx, int nz, int nsq) {
+        const float t = ma.tab[nsq];
+        if (f < 3) return mul_si<-1>(c_scale(x, t * (float)pick_comp(f, nx, ny, nz)));   // conj(i n_j t) X
+        const int na = pick_comp(hess_a(f - 3), nx, ny, nz);
+        const int nb = pick_comp(hess_b(f - 3), nx, ny, nz);
+        return c_scale(x, ma.kf * t * (float)(na * nb));                                   // real multiplier
+      });
     }
   }
   __syncthreads();
-#pragma unroll
-  for (int i = 0; i < PER; ++i) {
-    const int idx = threadIdx.x + i * T;
-    if (FULL || idx < N * B) tile[idx] = acc[i];
-  }
-  __syncthreads();
-  fft_tile<N, B, T, B, 1, false, 1, 1>(tile, stw);
-  col_store<N, B, T>(tile, out + origin, inner);
+  float2 r[P::R2];
+  P::template inv_like<1, 1>(acc, r, ex, stw);
+  P::store_a(r, out + origin, inner);
 }
 
 // ---------------------------------------------------------------------------------
@@ -397,31 +392,31 @@ bool fft_size_supported(int n) {
 
 template <int N>
 static hipError_t zfwd_t(const float* in, float2* out, long nrows, const float2* tw, hipStream_t st) {
-  constexpr int BR = z_rows<N>();
-  if (nrows % BR) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_zfwd<N>, dim3(nrows / BR), dim3(kThreads), 0, st, in, out, tw);
+  using P = ZPencil<N>;
+  if (nrows % P::NT) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zfwd<N>, dim3(nrows / P::NT), dim3(P::T), 0, st, in, out, tw);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t zinv_t(FieldPtrs in, FieldPtrs out, int nf, long nrows, const float2* tw, int epi,
                          EpiArgs e, hipStream_t st) {
-  constexpr int BR = z_rows<N>();
-  if (nrows % BR) return hipErrorInvalidValue;
-  dim3 grid(nrows / BR, nf);
+  using P = ZPencil<N>;
+  if (nrows % P::NT) return hipErrorInvalidValue;
+  dim3 grid(nrows / P::NT, nf);
   if (epi == kEpiStore)
-    hipLaunchKernelGGL((k_zinv<N, kEpiStore>), grid, dim3(kThreads), 0, st, in, out, tw, e);
+    hipLaunchKernelGGL((k_zinv<N, kEpiStore>), grid, dim3(P::T), 0, st, in, out, tw, e);
   else
-    hipLaunchKernelGGL((k_zinv<N, kEpiLptFinal>), grid, dim3(kThreads), 0, st, in, out, tw, e);
+    hipLaunchKernelGGL((k_zinv<N, kEpiLptFinal>), grid, dim3(P::T), 0, st, in, out, tw, e);
   return hipGetLastError();
 }
 
 template <int N>
 static hipError_t zinv_hess_t(FieldPtrs in, float* out, long nrows, const float2* tw, float scale,
                               hipStream_t st) {
-  constexpr int BR = zh_rows<N>();
-  if (nrows % BR) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_zinv_hess<N>, dim3(nrows / BR), dim3(kThreads), 0, st, in, out, tw, scale);
+  using P = ZHPencil<N>;
+  if (nrows % P::NT) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zinv_hess<N>, dim3(nrows / P::NT), dim3(P::T), 0, st, in, out, tw, scale);
   return hipGetLastError();
 }
 
@@ -430,7 +425,7 @@ static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_out
                          long inner_stride, int ncols, const float2* tw, hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
     if (ncols % B) return hipErrorInvalidValue;
-    constexpr int T = col_threads_for(N, B);
+    constexpr int T = Pencil<N, B, false>::T;
     const int ntc = ncols / B;
     dim3 grid((unsigned)((long)n_outer * ntc), nf);
     if (dir < 0)
@@ -446,7 +441,7 @@ static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_out
 template <int N>
 static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
                         long inner_stride, int ncols, const float2* tw, int width, hipStream_t st) {
-  switch (width ? width : col_width<N>()) {
+  switch (width ? width : col_width_default(N)) {
     case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
     case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
     case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
@@ -458,7 +453,8 @@ template <int N, int B>
 static hipError_t xmul_tb(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
                           hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
-    constexpr int T = col_threads_for(N, B);
+    constexpr int T = Pencil<N, B, false>::T;
+    if (mode == kMulGrad ? nout != 3 : (nout < 1 || nout > kMaxFields)) return hipErrorInvalidValue;
     dim3 grid(N * ((N / 2) / B));
     if (mode == kMulGrad)
       hipLaunchKernelGGL((k_xmul<N, B, kMulGrad>), grid, dim3(T), 0, st, in, out, nout, m, tw);
@@ -470,10 +466,9 @@ static hipError_t xmul_tb(int mode, const float2* in, FieldPtrs out, int nout, M
   }
 }
 
-// Default x-pass width: 8 columns where valid (the multi-output x pass holds the
-// forward spectrum in registers, so narrower tiles keep more blocks resident).
+// Default x-pass width: the widest valid tile (128-byte row segments at 16 columns).
 template <int N>
-constexpr int xmul_width() { return col_ok<N, 8>() ? 8 : col_width<N>(); }
+constexpr int xmul_width() { return col_width_default(N); }
 
 template <int N>
 static hipError_t xmul_t(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
@@ -490,7 +485,8 @@ template <int N>
 static hipError_t xmul_adj_t(int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
                              hipStream_t st) {
   constexpr int B = xmul_width<N>();
-  constexpr int T = col_threads_for(N, B);
+  constexpr int T = Pencil<N, B, false>::T;
+  if (mode == kMulGrad ? nin != 3 : (nin < 1 || nin > kMaxFields)) return hipErrorInvalidValue;
   dim3 grid(N * ((N / 2) / B));
   if (mode == kMulGrad)
     hipLaunchKernelGGL((k_xmul_adj<N, B, kMulGrad>), grid, dim3(T), 0, st, in, nin, out, m, tw);
