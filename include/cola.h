@@ -236,9 +236,12 @@ int cola_ensemble_launch(cola_ensemble ens, void *stream);
 /* Frees the graph (the caller synchronises any launch first).  NULL is accepted. */
 int cola_ensemble_destroy(cola_ensemble ens);
 
-/* Stage tracing (for profiling; off by default).  When enabled, every kernel launch
+/* Stage tracing (for profiling; off by default).  enable = 1: every kernel launch
  * of the calls above is bracketed by a pair of hipEvents recorded on the launch
- * stream.  cola_trace_read waits for the recorded events, fills ms[k] with the
+ * stream.  enable = 2: only each COLA step of cola_run (deposit through the gather,
+ * stage "run_step") is bracketed, so step times carry no per-kernel event cost.
+ * enable = 0 turns tracing off; other values return COLA_ERR_INVALID.
+ * cola_trace_read waits for the recorded events, fills ms[k] with the
  * summed elapsed milliseconds and launches[k] with the launch count of stage k
  * (k < cola_trace_stage_count(); n is the capacity of both arrays, which must be at
  * least that count) and clears the record.  Enabling or disabling clears it too.

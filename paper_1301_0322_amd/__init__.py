@@ -270,7 +270,8 @@ class Plan:
                                                     _stream(stream), path, ctypes.byref(used)))
         return bool(used.value)
 
-    def trace_enable(self, enable: bool = True):
+    def trace_enable(self, enable: int = 1):
+        """1: events around every kernel; 2: around each cola_run step only; 0: off."""
         _check("cola_trace_enable", lib().cola_trace_enable(self._c, int(enable)))
 
     def trace_read(self):

@@ -27,7 +27,7 @@ struct cola_plan_s {
   Bins bins;                      // Eulerian tiles of the force mesh
   int fft_width[2] = {0, 0};      // columns per tile of the mesh-size y passes and x pass (0: default)
   // stage tracing (hipEvent pairs around each launch, on the launch stream)
-  bool trace = false;
+  int trace = 0;   // trace level: 0 off, 1 every kernel, 2 each cola_run step
   std::vector<hipEvent_t> ev_pool;
   std::vector<int> ev_stage;       // stage id of event pair k (events 2k, 2k+1)
   size_t ev_used = 0;              // pairs recorded since the last read
@@ -50,38 +50,51 @@ int hip_status(hipError_t e) {
 
 // Stage ids reported by cola_trace_read.
 enum Stage : int {
-  kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStDepositMerge, kStZFwd, kStYFwd, kStXPoisson,
+  kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStZFwd, kStYFwd, kStXPoisson,
   kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
   kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kStAdjKick, kStAdjDeposit, kStAdjFft, kStAdjGather,
-  kStAdjLpt, kStCheckpoint, kNumStages
+  kStAdjLpt, kStCheckpoint, kStRunStep, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
-  "bin_count", "bin_scan", "bin_scatter", "deposit", "deposit_merge", "fft_z_fwd", "fft_y_fwd",
+  "bin_count", "bin_scan", "bin_scatter", "deposit", "fft_z_fwd", "fft_y_fwd",
   "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
   "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
-  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint"};
+  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step"};
 
-// Records an event pair around launch `fn` when tracing is on.
-template <class F>
-hipError_t traced(cola_plan p, int stage, hipStream_t st, F&& fn) {
-  if (!p->trace) return fn();
+// Trace levels: 1 records an event pair around every kernel launch, 2 only around
+// each whole COLA step of cola_run (stage run_step), so step times carry no
+// per-kernel event overhead.
+// trace_open returns the event slot of a span at `level`, or -1 when that level is
+// not being traced; trace_close records its end.
+long trace_open(cola_plan p, int level, int stage, hipStream_t st, hipError_t& rc) {
+  rc = hipSuccess;
+  if (p->trace != level) return -1;
   const size_t need = 2 * (p->ev_used + 1);
   while (p->ev_pool.size() < need) {
     hipEvent_t e;
-    const hipError_t rc = hipEventCreate(&e);
-    if (rc != hipSuccess) return rc;
+    rc = hipEventCreate(&e);
+    if (rc != hipSuccess) return -1;
     p->ev_pool.push_back(e);
   }
-  hipEvent_t e0 = p->ev_pool[2 * p->ev_used], e1 = p->ev_pool[2 * p->ev_used + 1];
-  hipError_t rc = hipEventRecord(e0, st);
+  const size_t slot = p->ev_used++;
+  if (p->ev_stage.size() <= slot) p->ev_stage.resize(slot + 1);
+  p->ev_stage[slot] = stage;
+  rc = hipEventRecord(p->ev_pool[2 * slot], st);
+  return (long)slot;
+}
+hipError_t trace_close(cola_plan p, long slot, hipStream_t st) {
+  return slot < 0 ? hipSuccess : hipEventRecord(p->ev_pool[2 * slot + 1], st);
+}
+
+// Runs launch `fn` inside a level-1 span.
+template <class F>
+hipError_t traced(cola_plan p, int stage, hipStream_t st, F&& fn) {
+  hipError_t rc;
+  const long slot = trace_open(p, 1, stage, st, rc);
   if (rc != hipSuccess) return rc;
   rc = fn();
   if (rc != hipSuccess) return rc;
-  rc = hipEventRecord(e1, st);
-  if (rc != hipSuccess) return rc;
-  if (p->ev_stage.size() <= p->ev_used) p->ev_stage.resize(p->ev_used + 1);
-  p->ev_stage[p->ev_used++] = stage;
-  return hipSuccess;
+  return trace_close(p, slot, st);
 }
 
 #define COLA_TRY(expr)                      \
@@ -216,7 +229,6 @@ int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t
   COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
   COLA_HIP(traced(p, kStDeposit, st,
                   [&] { return launch_deposit(lat, b, s, bb, rho, (float)(ratio * ratio * ratio), st); }));
-  COLA_HIP(traced(p, kStDepositMerge, st, [&] { return launch_deposit_merge(lat, b, bb, rho, st); }));
   return COLA_OK;
 }
 
@@ -427,7 +439,6 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
       COLA_HIP(traced(p, kStAdjDeposit, st, [&] {
         return launch_deposit(lat, b, s_i, bb, L.amesh[d], mass, st, L.lam_v + d * n);
       }));
-      COLA_HIP(traced(p, kStAdjDeposit, st, [&] { return launch_deposit_merge(lat, b, bb, L.amesh[d], st); }));
     }
     // rbar = sum_d K_d^T nu_d (conjugate multiplier), into amesh[0]
     const float2* tw = p->d_tw_nm;
@@ -710,8 +721,10 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
   const Bins& b = p->bins;
   const float mass = (float)std::pow((double)lat.ratio, 3);
   const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
-  // The state is kept sorted by tile in two workspace copies: every deposit writes
-  // the re-sorted copy, every gather bins the drifted particles for the next one.
+  // The state is kept sorted by tile in two workspace copies: every step reads the
+  // copy ordered by the previous step's tiles through this step's tile lists, and its
+  // gather writes the updated state, ordered by this step's tiles, to the other copy
+  // while binning the drifted particles for the next step.
   int parity = 0;
   BinBuffers bb = bin_buffers(p, ws, parity);
   COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, q->s, bb, st); }));
@@ -721,12 +734,14 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
   for (int i = 0; i <= p->cfg.n_steps; ++i) {
     const bool last = i == p->cfg.n_steps;
     const StepRow& row = p->table[i];
+    hipError_t trc;
+    const long span = last ? -1 : trace_open(p, 2, kStRunStep, st, trc);
+    if (!last) COLA_HIP(trc);
     bb = bin_buffers(p, ws, parity);
     COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, !last, st); }));
     COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
-    const SortedState dst = sorted_state(p, ws, which);
-    COLA_HIP(traced(p, kStDeposit, st, [&] { return launch_deposit_perm(lat, b, src, dst, bb, ws, mass, st); }));
-    COLA_HIP(traced(p, kStDepositMerge, st, [&] { return launch_deposit_merge(lat, b, bb, ws, st); }));
+    COLA_HIP(traced(p, kStDeposit, st,
+                    [&] { return launch_deposit(lat, b, src.s, bb, ws, mass, st, nullptr, src.lag); }));
     COLA_TRY(fft_force(p, row.a, ws, st));
     KickArgs k{};
     k.alpha = (float)row.alpha;
@@ -736,8 +751,10 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
       k.beta = (float)row.beta;
       k.dd1 = plain ? 0.0f : (float)row.dd1;
       k.dd2 = plain ? 0.0f : (float)row.dd2;
+      const SortedState dst = sorted_state(p, ws, which);
       COLA_HIP(traced(p, kStGatherKickDrift, st,
-                      [&] { return launch_gather_sorted(lat, b, dst, bb, kGatherKickDrift, g, k, st); }));
+                      [&] { return launch_gather_sorted(lat, b, src, dst, bb, kGatherKickDrift, g, k, st); }));
+      COLA_HIP(trace_close(p, span, st));
       parity ^= 1;
       src = dst;
       which ^= 1;
@@ -749,7 +766,8 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
       g.v = q->v;
       g.out_a = x_out;
       g.out_b = v_out;
-      COLA_HIP(traced(p, kStFinish, st, [&] { return launch_gather_sorted(lat, b, dst, bb, kGatherFinish, g, k, st); }));
+      COLA_HIP(traced(p, kStFinish, st,
+                      [&] { return launch_gather_sorted(lat, b, src, SortedState{}, bb, kGatherFinish, g, k, st); }));
     }
   }
   return COLA_OK;
@@ -1039,8 +1057,8 @@ int cola_ensemble_destroy(cola_ensemble e) {
 }
 
 int cola_trace_enable(cola_plan p, int enable) {
-  if (!p) return COLA_ERR_INVALID;
-  p->trace = enable != 0;
+  if (!p || enable < 0 || enable > 2) return COLA_ERR_INVALID;
+  p->trace = enable;
   p->ev_used = 0;
   return COLA_OK;
 }

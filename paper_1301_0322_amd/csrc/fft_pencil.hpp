@@ -143,7 +143,12 @@ struct Pencil {
   // [b2][j2] (stride R2+1) for the inverse one.  COL: [i1][j2][b] with i1 stride PF.
   static constexpr int SF = R2 * (R1 + 1), SI = R1 * (R2 + 1);
   static constexpr int PF = round_up(R2 * NT, 32) + NT;
-  static constexpr int LDS = ROW ? NT * pmax(SF, SI) : R1 * PF;
+  // COL tiles with several B-layout units per thread exchange in UB chunks of R1
+  // j2-columns (the j2 of B-layout slice u is in [u R1, (u+1) R1)), which divides the
+  // LDS of the exchange by UB and lets more tiles share a CU.
+  static constexpr bool CHUNK = !ROW && UB > 1;
+  static constexpr int PC = round_up(R1 * NT, 32) + NT;
+  static constexpr int LDS = ROW ? NT * pmax(SF, SI) : (CHUNK ? R1 * PC : R1 * PF);
 
   static_assert(R2 > 0 && R1 * R2 == L, "unsupported transform length");
   static_assert(R1 <= 32 && R2 <= 32, "register DFTs are at most 32 long");
@@ -218,16 +223,32 @@ struct Pencil {
     dft_reg<R2, S>(a);
 #pragma unroll
     for (int j2 = 1; j2 < R2; ++j2) a[j2] = c_mul(a[j2], tw_table<S, TWS>(tab, i1 * j2));
+    if constexpr (CHUNK) {
 #pragma unroll
-    for (int j2 = 0; j2 < R2; ++j2) ex[addr_f(b, i1, j2)] = a[j2];
-    __syncthreads();
+      for (int u = 0; u < UB; ++u) {
+        if (u > 0) __syncthreads();   // the previous chunk has been read
 #pragma unroll
-    for (int u = 0; u < UB; ++u) {
-      int bb, j2;
-      if (!b_unit(u, bb, j2)) continue;
+        for (int jj = 0; jj < R1; ++jj)
+          if (u * R1 + jj < R2) ex[i1 * PC + jj * NT + b] = a[u * R1 + jj];
+        __syncthreads();
+        int bb, j2;
+        if (!b_unit(u, bb, j2)) continue;
 #pragma unroll
-      for (int k = 0; k < R1; ++k) q[u][k] = ex[addr_f(bb, k, j2)];
-      dft_reg<R1, S>(q[u]);
+        for (int k = 0; k < R1; ++k) q[u][k] = ex[k * PC + (j2 - u * R1) * NT + bb];
+        dft_reg<R1, S>(q[u]);
+      }
+    } else {
+#pragma unroll
+      for (int j2 = 0; j2 < R2; ++j2) ex[addr_f(b, i1, j2)] = a[j2];
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        int bb, j2;
+        if (!b_unit(u, bb, j2)) continue;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) q[u][k] = ex[addr_f(bb, k, j2)];
+        dft_reg<R1, S>(q[u]);
+      }
     }
   }
 
@@ -242,14 +263,35 @@ struct Pencil {
       dft_reg<R1, S>(q[u]);
 #pragma unroll
       for (int b2 = 1; b2 < R1; ++b2) q[u][b2] = c_mul(q[u][b2], tw_table<S, TWS>(tab, j2 * b2));
-#pragma unroll
-      for (int b2 = 0; b2 < R1; ++b2) ex[addr_i(b, j2, b2)] = q[u][b2];
     }
-    __syncthreads();
     int b, b2;
     a_unit(b, b2);
+    if constexpr (CHUNK) {
 #pragma unroll
-    for (int j2 = 0; j2 < R2; ++j2) a[j2] = ex[addr_i(b, j2, b2)];
+      for (int u = 0; u < UB; ++u) {
+        if (u > 0) __syncthreads();   // the previous chunk has been read
+        int bu, j2;
+        if (b_unit(u, bu, j2)) {
+#pragma unroll
+          for (int k = 0; k < R1; ++k) ex[k * PC + (j2 - u * R1) * NT + bu] = q[u][k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int jj = 0; jj < R1; ++jj)
+          if (u * R1 + jj < R2) a[u * R1 + jj] = ex[b2 * PC + jj * NT + b];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        int bu, j2;
+        if (!b_unit(u, bu, j2)) continue;
+#pragma unroll
+        for (int k = 0; k < R1; ++k) ex[addr_i(bu, j2, k)] = q[u][k];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j2 = 0; j2 < R2; ++j2) a[j2] = ex[addr_i(b, j2, b2)];
+    }
     dft_reg<R2, S>(a);
   }
 

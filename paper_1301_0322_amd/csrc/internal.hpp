@@ -80,20 +80,22 @@ struct Lattice {
 
 hipError_t launch_fill(float* p, long n, float value, hipStream_t st);
 
-// Eulerian tiles of tx x ty x tz cells used to bin particles every step.
+// Eulerian tiles of tx x ty x tz cells used to bin particles every step.  Within a
+// tile, particles are further keyed by a 3-bit boundary class (bit d: the base cell
+// is on the tile's upper face along d); key = 8 tile + class.
 struct Bins {
   int tx, ty, tz;
   int nbx, nby, nbz;
   long nbins;
-  int halo;          // floats of halo faces stored per tile
+  long nkeys;        // 8 nbins
 };
 struct BinBuffers {
-  int2* key_rank;    // [npart] (tile, rank within tile)
-  int* idx;          // [npart] particle indices grouped by tile
-  int* count;        // [count_len] particles per tile
+  int2* key_rank;    // [npart] (key, rank within key)
+  int* idx;          // [npart] particle slots grouped by key
+  int* count;        // [count_len] particles per key
   int* count_next;   // [count_len] counts for the next step, filled by a binning gather
-  int* offset;       // [count_len] exclusive prefix sum, offset[nbins] = npart
-  float* halo;       // [nbins * halo] halo faces of each tile's deposit
+  int* offset;       // [count_len] exclusive prefix sum, offset[nkeys] = npart
+  int* part;         // scan chunk sums
   long count_len;
 };
 // Tile depth: the largest of 8, 16, 32 (<= tz_max) dividing nm.
@@ -105,12 +107,13 @@ hipError_t launch_bin_count(Lattice lat, Bins b, const float* s, BinBuffers bb, 
 // clear_next also zeroes count_next for a binning gather later in the step.
 hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t st);
 hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
-// Tile deposit (cells written with plain stores, halo faces to the side buffer)
-// followed by the merge of the halo faces.  rho needs no clearing.
-// weight (optional, [np^3] in Lagrangian order): particle p carries mass * weight[p].
+// Tile deposit: each tile accumulates its own particles and the boundary classes of
+// its lower neighbours that reach into it, then writes its cells with plain stores.
+// rho needs no clearing.  bb.idx lists slots of s by key; lag (optional) gives a
+// slot's Lagrangian index (the slot itself when null).  weight (optional, [np^3] by
+// Lagrangian index): the particle carries mass * weight.
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                          hipStream_t st, const float* weight = nullptr);
-hipError_t launch_deposit_merge(Lattice lat, Bins b, BinBuffers bb, float* rho, hipStream_t st);
+                          hipStream_t st, const float* weight = nullptr, const int* lag = nullptr);
 
 struct KickArgs {
   float alpha;                 // kick factor
@@ -142,8 +145,7 @@ hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_
                          hipStream_t st);
 
 // Particle state ordered by tile (slot j), with each particle's Lagrangian index.
-// As a deposit_perm source, lag == nullptr means slot = Lagrangian index (the
-// caller's arrays).
+// lag == nullptr means slot = Lagrangian index (the caller's arrays).
 struct SortedState {
   float* s;
   float* v;
@@ -151,15 +153,13 @@ struct SortedState {
   float* s2;
   int* lag;
 };
-// Deposit that also permutes src into dst in tile order (dst slot j holds the
-// particle src slot idx[j]).
-hipError_t launch_deposit_perm(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, float* rho,
-                               float mass, hipStream_t st);
-// Gather + kick on the sorted state.  kGatherKickDrift drifts in place and bins the
-// drifted particles (bb.count_next, bb.key_rank by slot); kGatherFinish writes the
-// final s, v, x and v_phys in Lagrangian order through a.s, a.v, a.out_a, a.out_b.
-hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a,
-                                KickArgs k, hipStream_t st);
+// Gather + kick over the tile lists bb.idx (slots of src).  kGatherKickDrift writes
+// the kicked and drifted record of list position j to slot j of dst (ordered by this
+// step's tiles) and bins it for the next step (bb.count_next, bb.key_rank by dst slot);
+// kGatherFinish writes the final s, v, x and v_phys in Lagrangian order through a.s,
+// a.v, a.out_a, a.out_b.
+hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
+                                GatherArgs a, KickArgs k, hipStream_t st);
 
 // Adjoint kernels.
 struct AdjGatherArgs {

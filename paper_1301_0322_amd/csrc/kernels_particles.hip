@@ -38,29 +38,30 @@ __global__ __launch_bounds__(kPartThreads) void k_fill(float4* p, long n4, float
 // ---------------------------------------------------------------------------------
 // Eulerian binning.  The mesh is cut into tiles of tx x ty x tz cells; every step
 // the particles are binned by the tile of their base cell (the lower corner of
-// their CIC stencil), so that deposit and gather run tile by tile through LDS:
-//   bin_count   wavefront-aggregated atomics give each particle its rank in its
-//               tile (lanes sharing a tile take one atomic between them);
-//   bin_scan    exclusive prefix sum of the tile counts;
-//   bin_scatter idx[offset[tile] + rank] = p;
-//   deposit     per tile: LDS atomics over the tile plus its +1 halo, then plain
-//               stores of the tile's cells and of its halo faces to a side buffer;
-//   merge       per tile: add the lower neighbours' halo faces to the tile's low
-//               faces (every cell has one writer: no global float atomics);
-//   gather      per tile: the three force meshes over tile + halo read once into
-//               LDS, then every particle of the tile reads its 8 corners there.
+// their CIC stencil) and, within it, by a 3-bit boundary class: bit d is set when
+// the base cell lies on the tile's upper face along axis d, i.e. when the stencil
+// reaches into the next tile along d.  Key = 8 tile + class.  Deposit and gather
+// then run tile by tile through LDS:
+//   bin_count   wavefront-aggregated atomics give each particle its rank among the
+//               particles with its key (lanes sharing a key take one atomic);
+//   bin_scan    exclusive prefix sum of the key counts (tile t owns the particle
+//               range [offset[8t], offset[8t + 8]));
+//   bin_scatter idx[offset[key] + rank] = slot;
+//   deposit     per tile: its own particles plus the boundary classes of its seven
+//               lower neighbours that reach into it, accumulated in an LDS tile of
+//               exactly the tile's cells, which are then written with plain stores:
+//               every cell has one writer and no halo needs merging;
+//   gather      per tile: the three force meshes over tile + 1 read once into LDS,
+//               then every particle of the tile reads its 8 corners there.
 // ---------------------------------------------------------------------------------
 constexpr int kTX = 8, kTY = 8;   // tile cells along x and y; tz (8, 16 or 32) is a template parameter
+constexpr int kClasses = 8;
 
 template <int TZ>
 struct TileDims {
-  static constexpr int EY = kTY + 1, EZ = TZ + 1;           // extents with the +1 halo
+  static constexpr int EY = kTY + 1, EZ = TZ + 1;           // extents with the +1 halo (gather)
   static constexpr int EXT = (kTX + 1) * EY * EZ;
   static constexpr int CORE = kTX * kTY * TZ;
-  static constexpr int FX = EY * EZ;                         // face x = tx: y <= ty, z <= tz
-  static constexpr int FY = kTX * EZ;                        // face y = ty: x < tx, z <= tz
-  static constexpr int FZ = kTX * kTY;                       // face z = tz: x < tx, y < ty
-  static constexpr int HALO = FX + FY + FZ;
 };
 
 // Deposit accumulators.  A tile sums its CIC contributions in LDS either as FP32
@@ -110,28 +111,36 @@ __device__ __forceinline__ Stencil stencil_of(const Lattice& lat, unsigned p, co
 }
 
 template <int TZ>
-__device__ __forceinline__ int bin_of(const Bins& b, const int c[3]) {
-  return ((c[0] / kTX) * b.nby + c[1] / kTY) * b.nbz + c[2] / TZ;
+__device__ __forceinline__ int key_of(const Bins& b, const int c[3]) {
+  const int tile = ((c[0] / kTX) * b.nby + c[1] / kTY) * b.nbz + c[2] / TZ;
+  const int cls = ((c[0] % kTX) == kTX - 1) | (((c[1] % kTY) == kTY - 1) << 1) | (((c[2] % TZ) == TZ - 1) << 2);
+  return tile * kClasses + cls;
 }
 
 // Rank of each active lane among the lanes of its wave with the same bin, plus one
 // atomic per distinct bin that reserves the ranks.  Called by every lane of the wave.
+// The ballot loop only groups the lanes; the group leaders then issue their atomics
+// together, so a wave waits for one atomic round trip whatever its number of bins.
 __device__ __forceinline__ int wave_rank(bool active, int bin, int* __restrict__ count) {
   const int lane = __lane_id();
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   unsigned long long pending = __ballot(active);
-  int rank = 0;
+  int leader = lane, below = 0, members = 0;
   while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int lb = __shfl(bin, leader);
+    const int first = __ffsll((long long)pending) - 1;
+    const int lb = __shfl(bin, first);
     const unsigned long long m = __ballot(active && bin == lb);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(count + lb, __popcll(m));
-    base = __shfl(base, leader);
-    if (active && bin == lb) rank = base + __popcll(m & lt);
+    if (active && bin == lb) {
+      leader = first;
+      below = __popcll(m & lt);
+      members = __popcll(m);
+    }
     pending &= ~m;
   }
-  return rank;
+  int base = 0;
+  if (active && lane == leader) base = atomicAdd(count + bin, members);
+  base = __shfl(base, leader);
+  return base + below;
 }
 
 template <int TZ>
@@ -143,47 +152,107 @@ __global__ __launch_bounds__(kPartThreads) void k_bin_count(Lattice lat, Bins bi
   if (ok) {
     const float sv[3] = {s[p], s[lat.npart + p], s[2 * lat.npart + p]};
     const Stencil st = stencil_of(lat, p, sv);
-    bin = bin_of<TZ>(bins, st.c);
+    bin = key_of<TZ>(bins, st.c);
   }
   const int rank = wave_rank(ok, bin, count);
   if (ok) key_rank[p] = make_int2(bin, rank);
 }
 
-// Exclusive scan of count[0..n) into offset[0..n] (offset[n] = total) by one block
-// of 16 waves, each owning a contiguous segment; also clears count_next[0..n_pad).
-__global__ __launch_bounds__(1024) void k_bin_scan(const int* __restrict__ count, int* __restrict__ offset, int n,
-                                                   int* __restrict__ count_next, int n_pad) {
-  __shared__ int wsum[16];
+// Exclusive scan of count[0..n) into offset[0..n] (offset[n] = total) in three
+// launches: chunk sums, a one-block scan of the chunk sums, and the chunk scans.
+// The first launch also clears count_next (the counts the next gather fills).
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 4 * kScanThreads;
+
+__device__ __forceinline__ int block_sum_1024(int v, int* wsum) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int seg = (n + 15) / 16;
-  const int lo = wave * seg, hi = min(n, lo + seg);
-  int sum = 0;
-  for (int i = lo + lane; i < hi; i += 64) sum += count[i];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
-  if (lane == 0) wsum[wave] = sum;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if (lane == 0) wsum[wave] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < kScanThreads / 64; ++w) t += wsum[w];
+  return t;
+}
+
+// Exclusive scan across the block of one value per thread; returns the prefix and
+// the block total.
+__device__ __forceinline__ int block_scan_1024(int v, int* wsum, int& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[wave] = inc;
   __syncthreads();
   int carry = 0;
-  for (int w = 0; w < wave; ++w) carry += wsum[w];
-  for (int c = lo; c < hi; c += 64) {
-    const int i = c + lane;
-    const int v = i < hi ? count[i] : 0;
-    int inc = v;
+  total = 0;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(inc, o);
-      if (lane >= o) inc += t;
-    }
-    if (i < hi) offset[i] = carry + inc - v;
-    carry += __shfl(inc, 63);
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    carry += (w < wave) ? wsum[w] : 0;
+    total += wsum[w];
   }
-  if (threadIdx.x == 0) {
-    int tot = 0;
-    for (int w = 0; w < 16; ++w) tot += wsum[w];
-    offset[n] = tot;
+  return carry + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const int* __restrict__ count, int n,
+                                                            int* __restrict__ part, int* __restrict__ count_next,
+                                                            int n_pad) {
+  __shared__ int wsum[kScanThreads / 64];
+  const long base = (long)blockIdx.x * kScanChunk;
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const long i = base + threadIdx.x + k * kScanThreads;
+    if (i < n) v += count[i];
   }
+  const int t = block_sum_1024(v, wsum);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
   if (count_next)
-    for (int i = threadIdx.x; i < n_pad; i += 1024) count_next[i] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const long i = base + threadIdx.x + k * kScanThreads;
+      if (i < n_pad) count_next[i] = 0;
+    }
+}
+
+// One block: exclusive scan of the nb chunk sums in place; total to *tot.
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int* __restrict__ part, int nb, int* __restrict__ tot) {
+  __shared__ int wsum[kScanThreads / 64];
+  int carry = 0;
+  for (int c = 0; c < nb; c += kScanThreads) {
+    const int i = c + threadIdx.x;
+    const int v = i < nb ? part[i] : 0;
+    int total;
+    const int ex = block_scan_1024(v, wsum, total);
+    if (i < nb) part[i] = carry + ex;
+    carry += total;
+    __syncthreads();   // wsum is reused by the next round
+  }
+  if (threadIdx.x == 0) *tot = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const int* __restrict__ count, int n,
+                                                              const int* __restrict__ part,
+                                                              int* __restrict__ offset) {
+  __shared__ int wsum[kScanThreads / 64];
+  const long base = (long)blockIdx.x * kScanChunk + 4 * threadIdx.x;
+  int v[4], s4 = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? count[base + k] : 0;
+    s4 += v[k];
+  }
+  int total;
+  int run = part[blockIdx.x] + block_scan_1024(s4, wsum, total);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) offset[base + k] = run;
+    run += v[k];
+  }
 }
 
 __global__ __launch_bounds__(kPartThreads) void k_bin_scatter(long npart, const int2* __restrict__ key_rank,
@@ -212,14 +281,15 @@ __device__ __forceinline__ bool tile_geom(const Bins& b, TileGeom& g) {
   return true;
 }
 
-// Tile-local stencil of particle p; false if its base cell is not in this tile
-// (never the case: binning used the same arithmetic).
+// Tile-local stencil of the particle in slot `slot` of s with Lagrangian index `lagi`;
+// false if its base cell is not in this tile (never the case: binning used the same
+// arithmetic).
 template <int TZ>
-__device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom& g, const float* s, unsigned p,
-                                              float sv[3], int lc[3], float fr[3]) {
+__device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom& g, const float* s, unsigned slot,
+                                              unsigned lagi, float sv[3], int lc[3], float fr[3]) {
 #pragma unroll
-  for (int d = 0; d < 3; ++d) sv[d] = s[d * lat.npart + p];
-  const Stencil st = stencil_of(lat, p, sv);
+  for (int d = 0; d < 3; ++d) sv[d] = s[d * lat.npart + slot];
+  const Stencil st = stencil_of(lat, lagi, sv);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     lc[d] = st.c[d] - g.lo[d];
@@ -260,114 +330,135 @@ __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const fl
   }
 }
 
-// Writes a deposited tile: core cells to rho (plain stores), the three +1 faces
-// to the tile's slot of the halo side buffer.
+// Deposit of one tile.  The particle ranges that reach into tile t are its own (all
+// classes) and, for each lower neighbour n = t - (dx, dy, dz) with (dx, dy, dz) in
+// {0,1}^3 \ 0, the classes containing every bit of the mask m = dx | 2 dy | 4 dz.
+// Those 1 + 19 ranges are flattened so the block's lanes take consecutive particles
+// across all of them.  A particle's position relative to tile t along axis d is its
+// local coordinate in its own tile, minus the tile extent when it comes from the
+// lower neighbour along d; its stencil corners inside tile t are added to the LDS
+// tile (accumulator ACC as above) and the tile's cells are then stored.
+//   ACC = unsigned long long: fixed-point sums (mass deposits); float: FP32 atomics
+//   (weighted deposits, whose weights have no bounded scale).
+// idx holds slots of s; lag (optional) maps a slot to its Lagrangian index (the slot
+// itself when null); weight is indexed by Lagrangian index.
+constexpr int kDepRanges = 20;
+
 template <int TZ, class ACC>
-__device__ __forceinline__ void write_tile(const Lattice& lat, const TileGeom& g, const ACC* tile,
-                                           float* __restrict__ rho, float* __restrict__ halo) {
+__global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
+                                                                const int* __restrict__ lag,
+                                                                const int* __restrict__ idx,
+                                                                const int* __restrict__ offset, float* __restrict__ rho,
+                                                                float mass, const float* __restrict__ weight) {
   using D = TileDims<TZ>;
+  __shared__ ACC tile[D::CORE];
+  __shared__ int rbeg[kDepRanges], rpre[kDepRanges + 1], rmask[kDepRanges];
+  TileGeom g;
+  if (!tile_geom<TZ>(bins, g)) return;
+  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) tile[i] = 0;
+  if (threadIdx.x < 64) {
+    // lane r < 20 describes range r: r = 0 own tile, then the (mask, class) pairs
+    const int lane = threadIdx.x;
+    int beg = 0, len = 0, mask = 0;
+    if (lane < kDepRanges) {
+      int cls = 0;
+      if (lane > 0) {
+        // enumerate (mask, class) with (class & mask) == mask, mask != 0
+        int k = lane - 1;
+        for (int m = 1; m < 8; ++m) {
+          const int nc = 8 >> __popc(m);   // classes containing mask m
+          if (k < nc) {
+            mask = m;
+            // k-th class containing m: spread k over the bits not in m
+            int c = m, bit = 0;
+            for (int q = 0; q < 3; ++q)
+              if (!(m & (1 << q))) {
+                if (k & (1 << bit)) c |= 1 << q;
+                ++bit;
+              }
+            cls = c;
+            break;
+          }
+          k -= nc;
+        }
+      }
+      const int bx = g.lo[0] / kTX, by = g.lo[1] / kTY, bz = g.lo[2] / TZ;
+      const int nx = (mask & 1) ? (bx + bins.nbx - 1) % bins.nbx : bx;
+      const int ny = (mask & 2) ? (by + bins.nby - 1) % bins.nby : by;
+      const int nz = (mask & 4) ? (bz + bins.nbz - 1) % bins.nbz : bz;
+      const long key = (((long)nx * bins.nby + ny) * bins.nbz + nz) * kClasses;
+      if (lane == 0) {
+        beg = offset[key];
+        len = offset[key + kClasses] - beg;
+      } else {
+        beg = offset[key + cls];
+        len = offset[key + cls + 1] - beg;
+      }
+    }
+    int inc = len;
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+      const int t = __shfl_up(inc, o);
+      if (lane >= o) inc += t;
+    }
+    if (lane < kDepRanges) {
+      rbeg[lane] = beg;
+      rpre[lane + 1] = inc;
+      rmask[lane] = mask;
+    }
+    if (lane == 0) rpre[0] = 0;
+  }
+  __syncthreads();
+  const int total = rpre[kDepRanges];
+  constexpr int U = 2;   // particles per lane per batch, so their dependent loads overlap
+  for (int base = 0; base < total; base += U * kPartThreads) {   // block-uniform trip count
+    float sv[U][3];
+    unsigned lg[U];
+    int msk[U];
+    bool in[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = base + u * kPartThreads + (int)threadIdx.x;
+      in[u] = i < total;
+      const int ii = in[u] ? i : 0;
+      int r = 0;
+#pragma unroll
+      for (int q = 1; q < kDepRanges; ++q) r += (rpre[q] <= ii) ? 1 : 0;
+      msk[u] = rmask[r];
+      const unsigned slot = in[u] ? (unsigned)idx[rbeg[r] + ii - rpre[r]] : 0u;
+      lg[u] = lag ? (unsigned)lag[slot] : slot;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sv[u][d] = s[d * lat.npart + slot];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!in[u]) continue;
+      const Stencil st = stencil_of(lat, lg[u], sv[u]);
+      const int rx = (st.c[0] % kTX) - ((msk[u] & 1) ? kTX : 0);
+      const int ry = (st.c[1] % kTY) - ((msk[u] & 2) ? kTY : 0);
+      const int rz = (st.c[2] % TZ) - ((msk[u] & 4) ? TZ : 0);
+      const float mw = weight ? mass * weight[lg[u]] : mass;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int x = rx + a;
+        if ((unsigned)x >= (unsigned)kTX) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int y = ry + b;
+          if ((unsigned)y >= (unsigned)kTY) continue;
+          const float wab = mw * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
+          ACC* row = tile + (x * kTY + y) * TZ;
+          if ((unsigned)rz < (unsigned)TZ) tile_add(row + rz, wab * (1.f - st.f[2]));
+          if ((unsigned)(rz + 1) < (unsigned)TZ) tile_add(row + rz + 1, wab * st.f[2]);
+        }
+      }
+    }
+  }
+  __syncthreads();
   const long nm = lat.nm;
   for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
     const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
-    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile_value(tile[(x * D::EY + y) * D::EZ + z]);
-  }
-  float* h = halo + (long)g.bin * D::HALO;
-  for (int i = threadIdx.x; i < D::FX; i += kPartThreads) h[i] = tile_value(tile[kTX * D::EY * D::EZ + i]);
-  for (int i = threadIdx.x; i < D::FY; i += kPartThreads) {
-    const int x = i / D::EZ, z = i % D::EZ;
-    h[D::FX + i] = tile_value(tile[(x * D::EY + kTY) * D::EZ + z]);
-  }
-  for (int i = threadIdx.x; i < D::FZ; i += kPartThreads) {
-    const int x = i / kTY, y = i % kTY;
-    h[D::FX + D::FY + i] = tile_value(tile[(x * D::EY + y) * D::EZ + TZ]);
-  }
-}
-
-// ACC = unsigned long long: fixed-point sums (mass deposits); float: FP32 atomics
-// (weighted deposits, whose weights have no bounded scale).
-template <int TZ, class ACC>
-__global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
-                                                                const int* __restrict__ idx,
-                                                                const int* __restrict__ offset, float* __restrict__ rho,
-                                                                float* __restrict__ halo, float mass,
-                                                                const float* __restrict__ weight) {
-  using D = TileDims<TZ>;
-  __shared__ ACC tile[D::EXT];
-  TileGeom g;
-  if (!tile_geom<TZ>(bins, g)) return;
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0;
-  __syncthreads();
-  const int beg = offset[g.bin], end = offset[g.bin + 1];
-  // two particles per lane per iteration so their dependent loads overlap
-  for (int i = beg + threadIdx.x; i < end; i += 2 * kPartThreads) {
-    float sv[2][3], fr[2][3];
-    int lc[2][3];
-    bool ok[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int j = i + u * kPartThreads;
-      ok[u] = local_stencil<TZ>(lat, g, s, (unsigned)idx[j < end ? j : i], sv[u], lc[u], fr[u]) && j < end;
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (!ok[u]) continue;
-      const float mw = weight ? mass * weight[idx[i + u * kPartThreads]] : mass;
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const float wab = mw * (a ? fr[u][0] : 1.f - fr[u][0]) * (b ? fr[u][1] : 1.f - fr[u][1]);
-          ACC* row = tile + ((lc[u][0] + a) * D::EY + lc[u][1] + b) * D::EZ + lc[u][2];
-          tile_add(row, wab * (1.f - fr[u][2]));
-          tile_add(row + 1, wab * fr[u][2]);
-        }
-    }
-  }
-  __syncthreads();
-  write_tile<TZ>(lat, g, tile, rho, halo);
-}
-
-// Adds the lower neighbours' halo faces onto the tile's cells with a zero local
-// coordinate.
-template <int TZ>
-__global__ __launch_bounds__(kPartThreads) void k_deposit_merge(Lattice lat, Bins bins, float* __restrict__ rho,
-                                                                const float* __restrict__ halo) {
-  using D = TileDims<TZ>;
-  TileGeom g;
-  if (!tile_geom<TZ>(bins, g)) return;
-  const int bx = g.lo[0] / kTX, by = g.lo[1] / kTY, bz = g.lo[2] / TZ;
-  const int mx = (bx + bins.nbx - 1) % bins.nbx, my = (by + bins.nby - 1) % bins.nby,
-            mz = (bz + bins.nbz - 1) % bins.nbz;
-  auto face = [&](int X, int Y, int Z) { return halo + (((long)X * bins.nby + Y) * bins.nbz + Z) * D::HALO; };
-  const float* hx = face(mx, by, bz);
-  const float* hy = face(bx, my, bz);
-  const float* hz = face(bx, by, mz);
-  const float* hxy = face(mx, my, bz);
-  const float* hxz = face(mx, by, mz);
-  const float* hyz = face(bx, my, mz);
-  const float* hxyz = face(mx, my, mz);
-  constexpr int NA = kTY * TZ, NB = (kTX - 1) * TZ, NC = (kTX - 1) * (kTY - 1);
-  const long nm = lat.nm;
-  for (int i = threadIdx.x; i < NA + NB + NC; i += kPartThreads) {
-    int x, y, z;
-    if (i < NA) {
-      x = 0; y = i / TZ; z = i % TZ;
-    } else if (i < NA + NB) {
-      const int j = i - NA;
-      x = 1 + j / TZ; y = 0; z = j % TZ;
-    } else {
-      const int j = i - NA - NB;
-      x = 1 + j / (kTY - 1); y = 1 + j % (kTY - 1); z = 0;
-    }
-    float acc = 0.f;
-    if (x == 0) acc += hx[y * D::EZ + z];
-    if (y == 0) acc += hy[D::FX + x * D::EZ + z];
-    if (z == 0) acc += hz[D::FX + D::FY + x * kTY + y];
-    if (x == 0 && y == 0) acc += hxy[kTY * D::EZ + z];
-    if (x == 0 && z == 0) acc += hxz[y * D::EZ + TZ];
-    if (y == 0 && z == 0) acc += hyz[D::FX + x * D::EZ + TZ];
-    if (x == 0 && y == 0 && z == 0) acc += hxyz[kTY * D::EZ + TZ];
-    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] += acc;
+    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile_value(tile[i]);
   }
 }
 
@@ -390,13 +481,13 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
   }
   __syncthreads();
   const long n = lat.npart;
-  const int beg = offset[t.bin], end = offset[t.bin + 1];
+  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
   for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
     const int i = base + threadIdx.x;
     const unsigned p = (unsigned)idx[i < end ? i : base];
     float sv[3], fr[3];
     int lc[3];
-    const bool act = local_stencil<TZ>(lat, t, g.s, p, sv, lc, fr) && i < end;
+    const bool act = local_stencil<TZ>(lat, t, g.s, p, p, sv, lc, fr) && i < end;
     float f[3] = {0.f, 0.f, 0.f};
     if (act) {
 #pragma unroll
@@ -440,7 +531,7 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
     }
     if constexpr (BIN_NEXT) {
       int bin = 0;
-      if (act) bin = bin_of<TZ>(bins, stencil_of(lat, p, snew).c);
+      if (act) bin = key_of<TZ>(bins, stencil_of(lat, p, snew).c);
       const int rank = wave_rank(act, bin, count_next);
       if (act) key_rank_next[p] = make_int2(bin, rank);
     }
@@ -474,12 +565,12 @@ __global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins 
   }
   __syncthreads();
   const long n = lat.npart;
-  const int beg = offset[t.bin], end = offset[t.bin + 1];
+  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
   for (int i = beg + threadIdx.x; i < end; i += kPartThreads) {
     const unsigned p = (unsigned)idx[i];
     float sv[3], fr[3];
     int lc[3];
-    if (!local_stencil<TZ>(lat, t, s, p, sv, lc, fr)) continue;   // cannot happen
+    if (!local_stencil<TZ>(lat, t, s, p, p, sv, lc, fr)) continue;   // cannot happen
     float mu[3] = {0.f, 0.f, 0.f};
     if (with_g) {
 #pragma unroll
@@ -517,12 +608,13 @@ __global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins 
 
 // ---------------------------------------------------------------------------------
 // Tile-sorted particle state (used by whole runs).  The state lives in workspace
-// buffers ordered by the tile of the particles' current base cell, with each
-// particle's Lagrangian index stored beside it:
-//   deposit_perm  per destination tile: reads the previous buffer through idx (runs
-//                 of consecutive source slots), writes the sorted copy and deposits;
-//   gather_sorted per tile: coalesced gather + kick + drift on the sorted copy, then
-//                 counts the drifted particles into next step's tiles.
+// buffers ordered by the tiles of the previous step, with each particle's Lagrangian
+// index stored beside it.  A step reads it through this step's tile lists (idx: runs
+// of mostly consecutive slots, since particles move a few cells per step):
+//   deposit       per tile: positions and Lagrangian indices only (k_deposit_tiles);
+//   gather_sorted per tile: gather + kick + drift, the whole updated record written
+//                 to slot j of the other buffer (ordered by this step's tiles, so
+//                 coalesced), and the drifted particle counted into next step's tile.
 // ---------------------------------------------------------------------------------
 // One particle's state at slot j.  A state without a lag array (the caller's
 // arrays, in Lagrangian order) has lag = j.
@@ -542,66 +634,9 @@ __device__ __forceinline__ void load_record(const SortedState& st, long n, int j
   }
 }
 
-template <int TZ>
-__global__ __launch_bounds__(kPartThreads) void k_deposit_perm(Lattice lat, Bins bins, SortedState src,
-                                                               SortedState dst, const int* __restrict__ idx,
-                                                               const int* __restrict__ offset, float* __restrict__ rho,
-                                                               float* __restrict__ halo, float mass) {
-  using D = TileDims<TZ>;
-  constexpr int U = 2;   // particles per lane per batch, so their dependent reads overlap
-  __shared__ unsigned long long tile[D::EXT];   // fixed-point sums
-  TileGeom g;
-  if (!tile_geom<TZ>(bins, g)) return;
-  const long n = lat.npart;
-  const int beg = offset[g.bin], end = offset[g.bin + 1];
-  for (int i = threadIdx.x; i < D::EXT; i += kPartThreads) tile[i] = 0;
-  for (int base = beg; base < end; base += U * kPartThreads) {   // block-uniform trip count
-    SortedRecord r[U];
-    bool in[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int j = base + u * kPartThreads + (int)threadIdx.x;
-      in[u] = j < end;
-      load_record(src, n, idx[in[u] ? j : base], r[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (!in[u]) continue;
-      const int j = base + u * kPartThreads + (int)threadIdx.x;
-      dst.lag[j] = (int)r[u].lag;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        dst.s[d * n + j] = r[u].s[d];
-        dst.v[d * n + j] = r[u].v[d];
-        dst.s1[d * n + j] = r[u].s1[d];
-        dst.s2[d * n + j] = r[u].s2[d];
-      }
-    }
-    if (base == beg) __syncthreads();   // the zeroed tile is complete before the first adds
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const Stencil st = stencil_of(lat, r[u].lag, r[u].s);
-      const int lc[3] = {st.c[0] - g.lo[0], st.c[1] - g.lo[1], st.c[2] - g.lo[2]};
-      if (!in[u] || (unsigned)lc[0] >= (unsigned)kTX || (unsigned)lc[1] >= (unsigned)kTY ||
-          (unsigned)lc[2] >= (unsigned)TZ)
-        continue;   // out of the tile cannot happen: binning used the same arithmetic
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const float wab = mass * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
-          unsigned long long* row = tile + ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
-          tile_add(row, wab * (1.f - st.f[2]));
-          tile_add(row + 1, wab * st.f[2]);
-        }
-    }
-  }
-  __syncthreads();
-  write_tile<TZ>(lat, g, tile, rho, halo);
-}
-
 template <int TZ, int MODE>
-__global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bins bins, SortedState st_,
+__global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bins bins, SortedState src,
+                                                                SortedState dst, const int* __restrict__ idx,
                                                                 const int* __restrict__ offset, GatherArgs g,
                                                                 KickArgs k, int2* __restrict__ key_rank_next,
                                                                 int* __restrict__ count_next) {
@@ -610,11 +645,12 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
   TileGeom t;
   if (!tile_geom<TZ>(bins, t)) return;
   const long n = lat.npart;
-  const int beg = offset[t.bin], end = offset[t.bin + 1];
+  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
   // The first batch of particle reads is issued before the force tile is staged,
-  // so both are in flight together (most tiles hold one batch or less).
-  SortedRecord r;
-  if (beg < end) load_record(st_, n, min(beg + (int)threadIdx.x, end - 1), r);
+  // so both are in flight together (most tiles hold one batch or less); in crowded
+  // tiles each batch's reads are issued before the previous batch is processed.
+  SortedRecord r, rn;
+  if (beg < end) load_record(src, n, idx[min(beg + (int)threadIdx.x, end - 1)], r);
   {
     const float* f[3] = {g.g0, g.g1, g.g2};
     stage_fields<TZ, 3>(t, lat.nm, f, tile);
@@ -623,9 +659,12 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
   for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
     const int j = base + threadIdx.x;
     const bool in = j < end;
-    if (base != beg) load_record(st_, n, in ? j : base, r);
+    const int nbase = base + kPartThreads;
+    if (nbase < end) load_record(src, n, idx[min(nbase + (int)threadIdx.x, end - 1)], rn);
     const Stencil sc = stencil_of(lat, r.lag, r.s);
     const int lc[3] = {sc.c[0] - t.lo[0], sc.c[1] - t.lo[1], sc.c[2] - t.lo[2]};
+    // Always true for a listed particle (binning used the same arithmetic); the
+    // test only keeps the LDS reads in bounds.
     const bool act =
         in && (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
     float f[3] = {0.f, 0.f, 0.f};
@@ -642,15 +681,18 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
         }
     }
     float snew[3] = {r.s[0], r.s[1], r.s[2]};
-    if (act) {
+    if (in) {
+      if constexpr (MODE == kGatherKickDrift) dst.lag[j] = (int)r.lag;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const float a1 = r.s1[d], a2 = r.s2[d];
         const float v = r.v[d] + k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
         if constexpr (MODE == kGatherKickDrift) {
           snew[d] = r.s[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
-          st_.v[d * n + j] = v;
-          st_.s[d * n + j] = snew[d];
+          dst.s[d * n + j] = snew[d];
+          dst.v[d * n + j] = v;
+          dst.s1[d * n + j] = a1;
+          dst.s2[d * n + j] = a2;
         } else {
           // finish: state back to Lagrangian order, positions and full velocities out
           const unsigned lag = r.lag;
@@ -668,10 +710,11 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
     }
     if constexpr (MODE == kGatherKickDrift) {
       int bin = 0;
-      if (act) bin = bin_of<TZ>(bins, stencil_of(lat, r.lag, snew).c);
-      const int rank = wave_rank(act, bin, count_next);
-      if (act) key_rank_next[j] = make_int2(bin, rank);
+      if (in) bin = key_of<TZ>(bins, stencil_of(lat, r.lag, snew).c);
+      const int rank = wave_rank(in, bin, count_next);
+      if (in) key_rank_next[j] = make_int2(bin, rank);
     }
+    r = rn;
   }
 }
 
@@ -732,15 +775,16 @@ Bins make_bins(int nm, int tz_max) {
   b.nby = nm / b.ty;
   b.nbz = nm / b.tz;
   b.nbins = (long)b.nbx * b.nby * b.nbz;
-  b.halo = (b.ty + 1) * (b.tz + 1) + b.tx * (b.tz + 1) + b.tx * b.ty;
+  b.nkeys = b.nbins * kClasses;
   return b;
 }
 
-static size_t count_len(const Bins& b) { return (size_t)((b.nbins + 4) / 4 * 4); }
+static size_t count_len(const Bins& b) { return (size_t)((b.nkeys + 4) / 4 * 4); }
+static size_t scan_chunks(const Bins& b) { return (size_t)((b.nkeys + kScanChunk - 1) / kScanChunk); }
 
 size_t bin_workspace_bytes(long npart, const Bins& b) {
   return npart * sizeof(int2) + npart * sizeof(int) + 3 * count_len(b) * sizeof(int) +
-         (size_t)b.nbins * b.halo * sizeof(float);
+         (scan_chunks(b) + 4) / 4 * 4 * sizeof(int);
 }
 
 BinBuffers carve_bins(void* base, long npart, const Bins& b) {
@@ -757,7 +801,7 @@ BinBuffers carve_bins(void* base, long npart, const Bins& b) {
   c += cnt * sizeof(int);
   bb.offset = reinterpret_cast<int*>(c);
   c += cnt * sizeof(int);
-  bb.halo = reinterpret_cast<float*>(c);
+  bb.part = reinterpret_cast<int*>(c);
   bb.count_len = (long)cnt;
   return bb;
 }
@@ -790,8 +834,12 @@ hipError_t launch_bin_count(Lattice lat, Bins b, const float* s, BinBuffers bb, 
 }
 
 hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t st) {
-  hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bb.count, bb.offset, (int)b.nbins,
+  const int n = (int)b.nkeys;
+  const unsigned nb = (unsigned)scan_chunks(b);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanThreads), 0, st, bb.count, n, bb.part,
                      clear_next ? bb.count_next : nullptr, (int)bb.count_len);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, bb.part, (int)nb, bb.offset + n);
+  hipLaunchKernelGGL(k_scan_chunks, dim3(nb), dim3(kScanThreads), 0, st, bb.count, n, bb.part, bb.offset);
   return hipGetLastError();
 }
 
@@ -802,20 +850,14 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 }
 
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                          hipStream_t st, const float* weight) {
+                          hipStream_t st, const float* weight, const int* lag) {
   if (weight)
     COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float>), dim3(tile_blocks(b)), dim3(kPartThreads),
-                                              0, st, lat, b, s, bb.idx, bb.offset, rho, bb.halo, mass, weight))
+                                              0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass, weight))
   else
     COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long>), dim3(tile_blocks(b)),
-                                              dim3(kPartThreads), 0, st, lat, b, s, bb.idx, bb.offset, rho, bb.halo,
-                                              mass, weight))
-  return hipGetLastError();
-}
-
-hipError_t launch_deposit_merge(Lattice lat, Bins b, BinBuffers bb, float* rho, hipStream_t st) {
-  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_merge<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
-                                            lat, b, rho, bb.halo));
+                                              dim3(kPartThreads), 0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass,
+                                              weight))
   return hipGetLastError();
 }
 
@@ -844,29 +886,23 @@ hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_
   return hipGetLastError();
 }
 
-hipError_t launch_deposit_perm(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, float* rho,
-                               float mass, hipStream_t st) {
-  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_deposit_perm<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st,
-                                            lat, b, src, dst, bb.idx, bb.offset, rho, bb.halo, mass));
-  return hipGetLastError();
-}
-
 template <int TZ>
-static void gather_sorted_tz(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a, KickArgs k,
-                             hipStream_t st) {
+static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
+                             GatherArgs a, KickArgs k, hipStream_t st) {
   const dim3 grid(tile_blocks(b)), block(kPartThreads);
   if (mode == kGatherKickDrift)
-    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, ss, bb.offset, a, k,
-                       bb.key_rank, bb.count_next);
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, src, dst, bb.idx,
+                       bb.offset, a, k, bb.key_rank, bb.count_next);
   else
-    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherFinish>), grid, block, 0, st, lat, b, ss, bb.offset, a, k,
-                       bb.key_rank, bb.count_next);
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherFinish>), grid, block, 0, st, lat, b, src, dst, bb.idx, bb.offset,
+                       a, k, bb.key_rank, bb.count_next);
 }
 
-hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState ss, BinBuffers bb, int mode, GatherArgs a,
-                                KickArgs k, hipStream_t st) {
+hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
+                                GatherArgs a, KickArgs k, hipStream_t st) {
   if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
-  COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, ss, bb, mode, a, k, st));
+  if (mode == kGatherKickDrift && (!dst.s || !dst.v || !dst.s1 || !dst.s2 || !dst.lag)) return hipErrorInvalidValue;
+  COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, src, dst, bb, mode, a, k, st));
   return hipGetLastError();
 }
 
