@@ -53,13 +53,13 @@ enum Stage : int {
   kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStZFwd, kStYFwd, kStXPoisson,
   kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
   kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kStAdjKick, kStAdjDeposit, kStAdjFft, kStAdjGather,
-  kStAdjLpt, kStCheckpoint, kStRunStep, kNumStages
+  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
   "bin_count", "bin_scan", "bin_scatter", "deposit", "fft_z_fwd", "fft_y_fwd",
   "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
   "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
-  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step"};
+  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort"};
 
 // Trace levels: 1 records an event pair around every kernel launch, 2 only around
 // each whole COLA step of cola_run (stage run_step), so step times carry no
@@ -766,8 +766,10 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
       g.v = q->v;
       g.out_a = x_out;
       g.out_b = v_out;
+      const SortedState out = sorted_state(p, ws, which);
       COLA_HIP(traced(p, kStFinish, st,
-                      [&] { return launch_gather_sorted(lat, b, src, SortedState{}, bb, kGatherFinish, g, k, st); }));
+                      [&] { return launch_gather_sorted(lat, b, src, out, bb, kGatherFinish, g, k, st); }));
+      COLA_HIP(traced(p, kStUnsort, st, [&] { return launch_unsort(lat, out, g, st); }));
     }
   }
   return COLA_OK;

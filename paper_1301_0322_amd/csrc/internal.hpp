@@ -156,10 +156,13 @@ struct SortedState {
 // Gather + kick over the tile lists bb.idx (slots of src).  kGatherKickDrift writes
 // the kicked and drifted record of list position j to slot j of dst (ordered by this
 // step's tiles) and bins it for the next step (bb.count_next, bb.key_rank by dst slot);
-// kGatherFinish writes the final s, v, x and v_phys in Lagrangian order through a.s,
-// a.v, a.out_a, a.out_b.
+// kGatherFinish writes the final s, v, x and v_phys at slot j of dst.s, dst.v,
+// dst.s1, dst.s2 and dst.lag[Lagrangian index] = j, for launch_unsort.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st);
+// Lagrangian order from a kGatherFinish output w: a.s, a.v, a.out_a, a.out_b take
+// s, v, x, v_phys.
+hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t st);
 
 // Adjoint kernels.
 struct AdjGatherArgs {

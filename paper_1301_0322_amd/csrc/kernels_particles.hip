@@ -268,15 +268,34 @@ struct TileGeom {
   int lo[3];
 };
 
+// Tile of this block.  Each XCD (blocks b with b % 8 = k) takes the slab of tile
+// planes bx in [k nbx/8, (k+1) nbx/8) and walks it with bz fastest, then bx, then by,
+// so a tile's z, x and y neighbours (whose cells overlap its +1 halo) run within a
+// few dozen blocks of it on the same XCD and share its L2.  Meshes with nbx not a
+// multiple of 8 fall back to the plain slab order.
 template <int TZ>
 __device__ __forceinline__ bool tile_geom(const Bins& b, TileGeom& g) {
   const long nb = (b.nbins + kXcds - 1) / kXcds * kXcds;
-  g.bin = (int)xcd_block(nb);
-  if (g.bin >= b.nbins) return false;
-  const int bz = g.bin % b.nbz;
-  const int r = g.bin / b.nbz;
-  g.lo[0] = (r / b.nby) * kTX;
-  g.lo[1] = (r % b.nby) * kTY;
+  int bx, by, bz;
+  if (b.nbx % kXcds == 0) {
+    const long local = (long)blockIdx.x / kXcds;
+    const int sx = b.nbx / kXcds;
+    if (local >= b.nbins / kXcds) return false;
+    bz = (int)(local % b.nbz);
+    const long r = local / b.nbz;
+    bx = (int)(blockIdx.x % kXcds) * sx + (int)(r % sx);
+    by = (int)(r / sx);
+    g.bin = (int)(((long)bx * b.nby + by) * b.nbz + bz);
+  } else {
+    g.bin = (int)xcd_block(nb);
+    if (g.bin >= b.nbins) return false;
+    bz = g.bin % b.nbz;
+    const int r = g.bin / b.nbz;
+    bx = r / b.nby;
+    by = r % b.nby;
+  }
+  g.lo[0] = bx * kTX;
+  g.lo[1] = by * kTY;
   g.lo[2] = bz * TZ;
   return true;
 }
@@ -694,19 +713,21 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
           dst.s1[d * n + j] = a1;
           dst.s2[d * n + j] = a2;
         } else {
-          // finish: state back to Lagrangian order, positions and full velocities out
-          const unsigned lag = r.lag;
-          g.v[d * n + lag] = v;
-          g.s[d * n + lag] = r.s[d];
-          g.out_b[d * n + lag] = v + k.td1 * a1 + k.td2 * a2;
+          // finish: s, v, x = (q + s) mod L and v_phys in this step's tile order
+          // (dst.s, dst.v, dst.s1, dst.s2 carry s, v, x, v_phys), and the slot of
+          // every Lagrangian index in dst.lag, for k_unsort
+          dst.s[d * n + j] = r.s[d];
+          dst.v[d * n + j] = v;
+          dst.s2[d * n + j] = v + k.td1 * a1 + k.td2 * a2;
           int li[3];
-          lag_index(lat, lag, li);
+          lag_index(lat, r.lag, li);
           float x = (float)li[d] * (k.box / (float)lat.np) + r.s[d];
           x = x - k.box * floorf(x / k.box);
           if (x >= k.box) x -= k.box;
-          g.out_a[d * n + lag] = x;
+          dst.s1[d * n + j] = x;
         }
       }
+      if constexpr (MODE == kGatherFinish) dst.lag[r.lag] = j;
     }
     if constexpr (MODE == kGatherKickDrift) {
       int bin = 0;
@@ -901,8 +922,41 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st) {
   if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
-  if (mode == kGatherKickDrift && (!dst.s || !dst.v || !dst.s1 || !dst.s2 || !dst.lag)) return hipErrorInvalidValue;
+  if (!dst.s || !dst.v || !dst.s1 || !dst.s2 || !dst.lag) return hipErrorInvalidValue;
   COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, src, dst, bb, mode, a, k, st));
+  return hipGetLastError();
+}
+
+// Lagrangian order from the finish output: element p of each output takes slot
+// inv[p] of its tile-ordered copy (s, v, x, v_phys in w.s, w.v, w.s1, w.s2).
+// A block covers a 4 x 4 x 16 block of the Lagrangian grid (when np allows), whose
+// particles sit in a few neighbouring tiles, so its scattered reads stay local; its
+// writes are runs of 16 consecutive elements.
+__global__ __launch_bounds__(kPartThreads) void k_unsort(int np, long n, SortedState w, GatherArgs g) {
+  long p;
+  if (np % 16 == 0) {
+    const int nbk = np / 16, nbj = np / 4;
+    const int b = blockIdx.x;
+    const int bk = b % nbk, bj = (b / nbk) % nbj, bi = b / (nbk * nbj);
+    const int t = threadIdx.x;
+    p = ((long)(4 * bi + t / 64) * np + 4 * bj + (t / 16) % 4) * np + 16 * bk + t % 16;
+  } else {
+    p = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  }
+  if (p >= n) return;
+  const long j = w.lag[p];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const long o = d * n;
+    g.s[o + p] = w.s[o + j];
+    g.v[o + p] = w.v[o + j];
+    g.out_a[o + p] = w.s1[o + j];
+    g.out_b[o + p] = w.s2[o + j];
+  }
+}
+
+hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t st) {
+  hipLaunchKernelGGL(k_unsort, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat.np, lat.npart, w, a);
   return hipGetLastError();
 }
 
