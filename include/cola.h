@@ -197,9 +197,11 @@ int cola_fft_c2r(cola_plan plan, int32_t n, const float *in, float *out, void *s
  * nm/2 or the tile would exceed 64 KB of LDS.  Host-only. */
 int cola_plan_set_fft_tile(cola_plan plan, int32_t pass, int32_t width);
 
-/* Depth in cells (8, 16 or 32) of the 8 x 8 x depth mesh tiles by which particles
- * are binned for the deposit and gather (a tuning knob; results agree up to FP32
- * summation order).  Call cola_workspace_bytes again afterwards.  Host-only. */
+/* Depth in cells (8, 16, 32 or 64) of the 8 x 8 x depth mesh tiles by which
+ * particles are binned for the deposit and gather (a tuning knob; results agree up to
+ * FP32 summation order).  COLA_ERR_INVALID for other depths, COLA_ERR_UNSUPPORTED_SIZE
+ * when depth does not divide nm.  Call cola_workspace_bytes again afterwards.
+ * Host-only. */
 int cola_plan_set_bin_depth(cola_plan plan, int32_t depth);
 
 /* Current tuning: y-pass and x-pass tile widths (0 = built-in default) and bin

@@ -847,7 +847,7 @@ int cola_plan_set_fft_tile(cola_plan p, int32_t pass, int32_t width) {
 }
 
 int cola_plan_set_bin_depth(cola_plan p, int32_t tz) {
-  if (!p || (tz != 8 && tz != 16 && tz != 32)) return COLA_ERR_INVALID;
+  if (!p || (tz != 8 && tz != 16 && tz != 32 && tz != 64)) return COLA_ERR_INVALID;
   if (p->cfg.nm % tz) return COLA_ERR_UNSUPPORTED_SIZE;
   p->bins = make_bins(p->cfg.nm, tz);
   return COLA_OK;
@@ -864,7 +864,7 @@ int cola_plan_get_tuning(cola_plan p, int32_t* y_width, int32_t* x_width, int32_
 int cola_tuning_workspace_bytes(cola_plan p, size_t* bytes) {
   if (!p || !bytes) return COLA_ERR_INVALID;
   size_t worst = 0;
-  for (int tz : {8, 16, 32})
+  for (int tz : {8, 16, 32, 64})
     if (p->cfg.nm % tz == 0) worst = std::max(worst, bin_workspace_bytes(cube(p->cfg.np), make_bins(p->cfg.nm, tz)));
   *bytes = mesh_floats(p) * sizeof(float) + worst;
   return COLA_OK;
@@ -893,7 +893,7 @@ int cola_autotune(cola_plan p, const cola_particles* q, void* ws_, size_t ws_byt
           std::string ks(k);
           while (!ks.empty() && ks.back() == ' ') ks.pop_back();
           if (ks == key && fft_width_supported(p->cfg.nm, y) && fft_width_supported(p->cfg.nm, x) &&
-              p->cfg.nm % tz == 0 && (tz == 8 || tz == 16 || tz == 32)) {
+              p->cfg.nm % tz == 0 && (tz == 8 || tz == 16 || tz == 32 || tz == 64)) {
             std::fclose(fh);
             p->fft_width[0] = y;
             p->fft_width[1] = x;
@@ -922,7 +922,7 @@ int cola_autotune(cola_plan p, const cola_particles* q, void* ws_, size_t ws_byt
   int rc = COLA_OK;
   const int widths[] = {4, 8, 16};
   (void)default_tz;
-  for (int tz : {8, 16, 32}) {
+  for (int tz : {8, 16, 32, 64}) {
     if (p->cfg.nm % tz) continue;
     if (bin_workspace_bytes(cube(p->cfg.np), make_bins(p->cfg.nm, tz)) > bin_cap) continue;
     p->bins = make_bins(p->cfg.nm, tz);

@@ -98,7 +98,7 @@ struct BinBuffers {
   int* part;         // scan chunk sums
   long count_len;
 };
-// Tile depth: the largest of 8, 16, 32 (<= tz_max) dividing nm.
+// Tile depth: the largest of 8, 16, 32, 64 (<= tz_max) dividing nm.
 Bins make_bins(int nm, int tz_max = 32);
 size_t bin_workspace_bytes(long npart, const Bins& b);
 BinBuffers carve_bins(void* base, long npart, const Bins& b);
@@ -140,7 +140,7 @@ struct GatherArgs {
   float* out_b;     // kGatherFinish: v_phys
 };
 // bin_next (kGatherKickDrift only): also count the drifted particles into
-// bb.count_next and write their (tile, rank) to bb.key_rank for the next step.
+// bb.count_next and write their (key, rank) to bb.key_rank for the next step.
 hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
                          hipStream_t st);
 
@@ -156,8 +156,10 @@ struct SortedState {
 // Gather + kick over the tile lists bb.idx (slots of src).  kGatherKickDrift writes
 // the kicked and drifted record of list position j to slot j of dst (ordered by this
 // step's tiles) and bins it for the next step (bb.count_next, bb.key_rank by dst slot);
-// kGatherFinish writes the final s, v, x and v_phys at slot j of dst.s, dst.v,
-// dst.s1, dst.s2 and dst.lag[Lagrangian index] = j, for launch_unsort.
+// kGatherFinish packs the final s, v, x and v_phys of slot j into three float4 at
+// float4 index j, n + j, 2n + j from dst.s (the 12 n floats dst.s .. dst.s2 are one
+// contiguous, 16-byte aligned block) and sets dst.lag[Lagrangian index] = j, for
+// launch_unsort.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st);
 // Lagrangian order from a kGatherFinish output w: a.s, a.v, a.out_a, a.out_b take

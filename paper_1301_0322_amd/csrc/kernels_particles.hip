@@ -62,6 +62,8 @@ struct TileDims {
   static constexpr int EY = kTY + 1, EZ = TZ + 1;           // extents with the +1 halo (gather)
   static constexpr int EXT = (kTX + 1) * EY * EZ;
   static constexpr int CORE = kTX * kTY * TZ;
+  // threads per tile block: a tile holds 2 TZ particles on average at mesh ratio 2
+  static constexpr int TT = TZ >= 64 ? 512 : kPartThreads;
 };
 
 // Deposit accumulators.  A tile sums its CIC contributions in LDS either as FP32
@@ -317,36 +319,55 @@ __device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom
   return (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
 }
 
-// Copies NF mesh fields over the tile's (8+1) x (8+1) x (TZ+1) extent (periodic
-// wrap) into LDS, field c at tile + c * EXT.  Every load of a lane is issued before
-// its first LDS write, so a block has all of its tile reads in flight at once.
+// Copies NF mesh fields over the cells (x, y, z) of the tile with x <= 8, y <= 8
+// (periodic wrap) and z < TZ into LDS, field c at tile + c * EXT, row stride EZ.
+// Each staged row is one aligned run of TZ floats (whole cache lines): the z = TZ
+// plane, which would add a line per row, is not staged; the few particles whose
+// stencil reaches it read those corners from the mesh (corner_value), where the
+// next tile along z, staged at the same time on the same XCD, keeps them in L2.
+// Every load of a lane is issued before its first LDS write, so a block has all of
+// its tile reads in flight at once.
 template <int TZ, int NF>
 __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const float* const* f, float* tile) {
   using D = TileDims<TZ>;
-  constexpr int IT = (D::EXT + kPartThreads - 1) / kPartThreads;
+  constexpr int NS = (kTX + 1) * D::EY * TZ;   // staged cells
+  constexpr int IT = (NS + D::TT - 1) / D::TT;
   float v[NF][IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    const int i = threadIdx.x + k * kPartThreads;
-    const int ii = i < D::EXT ? i : D::EXT - 1;
-    const int z = ii % D::EZ, r = ii / D::EZ;
+    const int i = threadIdx.x + k * D::TT;
+    const int ii = i < NS ? i : NS - 1;
+    const int z = ii % TZ, r = ii / TZ;
     const int y = r % D::EY, x = r / D::EY;
-    int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
+    int gx = t.lo[0] + x, gy = t.lo[1] + y;
     gx -= (gx >= nm) ? nm : 0;
     gy -= (gy >= nm) ? nm : 0;
-    gz -= (gz >= nm) ? nm : 0;
-    const long gi = ((long)gx * nm + gy) * nm + gz;
+    const long gi = ((long)gx * nm + gy) * nm + t.lo[2] + z;
 #pragma unroll
     for (int c = 0; c < NF; ++c) v[c][k] = f[c][gi];
   }
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
-    const int i = threadIdx.x + k * kPartThreads;
-    if (i < D::EXT) {
+    const int i = threadIdx.x + k * D::TT;
+    if (i < NS) {
+      const int z = i % TZ, r = i / TZ;
 #pragma unroll
-      for (int c = 0; c < NF; ++c) tile[c * D::EXT + i] = v[c][k];
+      for (int c = 0; c < NF; ++c) tile[c * D::EXT + r * D::EZ + z] = v[c][k];
     }
   }
+}
+
+// Field value at tile-local cell (x, y, z), x, y <= 8, z <= TZ: LDS offset o for
+// z < TZ, else the mesh (the first plane of the next tile along z, wrapped).
+template <int TZ>
+__device__ __forceinline__ float corner_value(const float* tile_field, const float* mesh, int o, const TileGeom& t,
+                                              int x, int y, int z, int nm) {
+  if (z < TZ) return tile_field[o];
+  int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + TZ;
+  gx -= (gx >= nm) ? nm : 0;
+  gy -= (gy >= nm) ? nm : 0;
+  gz -= (gz >= nm) ? nm : 0;
+  return mesh[((long)gx * nm + gy) * nm + gz];
 }
 
 // Deposit of one tile.  The particle ranges that reach into tile t are its own (all
@@ -364,7 +385,7 @@ __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const fl
 constexpr int kDepRanges = 20;
 
 template <int TZ, class ACC>
-__global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
+__global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
                                                                 const int* __restrict__ lag,
                                                                 const int* __restrict__ idx,
                                                                 const int* __restrict__ offset, float* __restrict__ rho,
@@ -374,7 +395,7 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bin
   __shared__ int rbeg[kDepRanges], rpre[kDepRanges + 1], rmask[kDepRanges];
   TileGeom g;
   if (!tile_geom<TZ>(bins, g)) return;
-  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) tile[i] = 0;
+  for (int i = threadIdx.x; i < D::CORE; i += D::TT) tile[i] = 0;
   if (threadIdx.x < 64) {
     // lane r < 20 describes range r: r = 0 own tile, then the (mask, class) pairs
     const int lane = threadIdx.x;
@@ -430,14 +451,14 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bin
   __syncthreads();
   const int total = rpre[kDepRanges];
   constexpr int U = 2;   // particles per lane per batch, so their dependent loads overlap
-  for (int base = 0; base < total; base += U * kPartThreads) {   // block-uniform trip count
+  for (int base = 0; base < total; base += U * D::TT) {   // block-uniform trip count
     float sv[U][3];
     unsigned lg[U];
     int msk[U];
     bool in[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int i = base + u * kPartThreads + (int)threadIdx.x;
+      const int i = base + u * D::TT + (int)threadIdx.x;
       in[u] = i < total;
       const int ii = in[u] ? i : 0;
       int r = 0;
@@ -475,7 +496,7 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bin
   }
   __syncthreads();
   const long nm = lat.nm;
-  for (int i = threadIdx.x; i < D::CORE; i += kPartThreads) {
+  for (int i = threadIdx.x; i < D::CORE; i += D::TT) {
     const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
     rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile_value(tile[i]);
   }
@@ -486,7 +507,7 @@ __global__ __launch_bounds__(kPartThreads) void k_deposit_tiles(Lattice lat, Bin
 // particles are also counted into next step's tiles (count_next, key_rank_next).
 // ---------------------------------------------------------------------------------
 template <int TZ, int MODE, bool BIN_NEXT>
-__global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins bins, const int* __restrict__ idx,
+__global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_tiles(Lattice lat, Bins bins, const int* __restrict__ idx,
                                                                const int* __restrict__ offset, GatherArgs g,
                                                                KickArgs k, int2* __restrict__ key_rank_next,
                                                                int* __restrict__ count_next) {
@@ -494,14 +515,13 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
   __shared__ float tile[3 * D::EXT];
   TileGeom t;
   if (!tile_geom<TZ>(bins, t)) return;
-  {
-    const float* f[3] = {g.g0, g.g1, g.g2};
-    stage_fields<TZ, 3>(t, lat.nm, f, tile);
-  }
+  const float* gf[3] = {g.g0, g.g1, g.g2};
+  const TileGeom& T_ = t;
+  stage_fields<TZ, 3>(t, lat.nm, gf, tile);
   __syncthreads();
   const long n = lat.npart;
   const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
-  for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
+  for (int base = beg; base < end; base += D::TT) {   // block-uniform trip count
     const int i = base + threadIdx.x;
     const unsigned p = (unsigned)idx[i < end ? i : base];
     float sv[3], fr[3];
@@ -517,7 +537,9 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
           const float w0 = wab * (1.f - fr[2]), w1 = wab * fr[2];
           const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) f[d] += w0 * tile[d * D::EXT + o] + w1 * tile[d * D::EXT + o + 1];
+          for (int d = 0; d < 3; ++d)
+            f[d] += w0 * tile[d * D::EXT + o] +
+                    w1 * corner_value<TZ>(tile + d * D::EXT, gf[d], o + 1, T_, lc[0] + a, lc[1] + b, lc[2] + 1, lat.nm);
         }
     }
     float snew[3] = {sv[0], sv[1], sv[2]};
@@ -567,7 +589,7 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_tiles(Lattice lat, Bins
 // given) and the density term through rbar = dL/drho.
 // ---------------------------------------------------------------------------------
 template <int TZ>
-__global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins bins, const int* __restrict__ idx,
+__global__ __launch_bounds__(TileDims<TZ>::TT) void k_grad_gather(Lattice lat, Bins bins, const int* __restrict__ idx,
                                                               const int* __restrict__ offset,
                                                               const float* __restrict__ s, AdjGatherArgs ga) {
   using D = TileDims<TZ>;
@@ -585,7 +607,7 @@ __global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins 
   __syncthreads();
   const long n = lat.npart;
   const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
-  for (int i = beg + threadIdx.x; i < end; i += kPartThreads) {
+  for (int i = beg + threadIdx.x; i < end; i += D::TT) {
     const unsigned p = (unsigned)idx[i];
     float sv[3], fr[3];
     int lc[3];
@@ -604,8 +626,12 @@ __global__ __launch_bounds__(kPartThreads) void k_grad_gather(Lattice lat, Bins 
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2] + c;
-          r[a][b][c] = tile[3 * D::EXT + o];
-          h[a][b][c] = with_g ? mu[0] * tile[o] + mu[1] * tile[D::EXT + o] + mu[2] * tile[2 * D::EXT + o] : 0.f;
+          const int x = lc[0] + a, y = lc[1] + b, z = lc[2] + c;
+          r[a][b][c] = corner_value<TZ>(tile + 3 * D::EXT, ga.rbar, o, t, x, y, z, lat.nm);
+          h[a][b][c] = with_g ? mu[0] * corner_value<TZ>(tile, ga.g0, o, t, x, y, z, lat.nm) +
+                                    mu[1] * corner_value<TZ>(tile + D::EXT, ga.g1, o, t, x, y, z, lat.nm) +
+                                    mu[2] * corner_value<TZ>(tile + 2 * D::EXT, ga.g2, o, t, x, y, z, lat.nm)
+                              : 0.f;
         }
     const float w[3][2] = {{1.f - fr[0], fr[0]}, {1.f - fr[1], fr[1]}, {1.f - fr[2], fr[2]}};
     float gh[3] = {0.f, 0.f, 0.f}, gr[3] = {0.f, 0.f, 0.f};
@@ -654,7 +680,7 @@ __device__ __forceinline__ void load_record(const SortedState& st, long n, int j
 }
 
 template <int TZ, int MODE>
-__global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bins bins, SortedState src,
+__global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat, Bins bins, SortedState src,
                                                                 SortedState dst, const int* __restrict__ idx,
                                                                 const int* __restrict__ offset, GatherArgs g,
                                                                 KickArgs k, int2* __restrict__ key_rank_next,
@@ -670,15 +696,14 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
   // tiles each batch's reads are issued before the previous batch is processed.
   SortedRecord r, rn;
   if (beg < end) load_record(src, n, idx[min(beg + (int)threadIdx.x, end - 1)], r);
-  {
-    const float* f[3] = {g.g0, g.g1, g.g2};
-    stage_fields<TZ, 3>(t, lat.nm, f, tile);
-  }
+  const float* gf[3] = {g.g0, g.g1, g.g2};
+  const TileGeom& T_ = t;
+  stage_fields<TZ, 3>(t, lat.nm, gf, tile);
   __syncthreads();
-  for (int base = beg; base < end; base += kPartThreads) {   // block-uniform trip count
+  for (int base = beg; base < end; base += D::TT) {   // block-uniform trip count
     const int j = base + threadIdx.x;
     const bool in = j < end;
-    const int nbase = base + kPartThreads;
+    const int nbase = base + D::TT;
     if (nbase < end) load_record(src, n, idx[min(nbase + (int)threadIdx.x, end - 1)], rn);
     const Stencil sc = stencil_of(lat, r.lag, r.s);
     const int lc[3] = {sc.c[0] - t.lo[0], sc.c[1] - t.lo[1], sc.c[2] - t.lo[2]};
@@ -696,10 +721,13 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
           const float w0 = wab * (1.f - sc.f[2]), w1 = wab * sc.f[2];
           const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
 #pragma unroll
-          for (int d = 0; d < 3; ++d) f[d] += w0 * tile[d * D::EXT + o] + w1 * tile[d * D::EXT + o + 1];
+          for (int d = 0; d < 3; ++d)
+            f[d] += w0 * tile[d * D::EXT + o] +
+                    w1 * corner_value<TZ>(tile + d * D::EXT, gf[d], o + 1, T_, lc[0] + a, lc[1] + b, lc[2] + 1, lat.nm);
         }
     }
     float snew[3] = {r.s[0], r.s[1], r.s[2]};
+    float vf[3], vp[3], xo[3];
     if (in) {
       if constexpr (MODE == kGatherKickDrift) dst.lag[j] = (int)r.lag;
 #pragma unroll
@@ -713,21 +741,26 @@ __global__ __launch_bounds__(kPartThreads) void k_gather_sorted(Lattice lat, Bin
           dst.s1[d * n + j] = a1;
           dst.s2[d * n + j] = a2;
         } else {
-          // finish: s, v, x = (q + s) mod L and v_phys in this step's tile order
-          // (dst.s, dst.v, dst.s1, dst.s2 carry s, v, x, v_phys), and the slot of
-          // every Lagrangian index in dst.lag, for k_unsort
-          dst.s[d * n + j] = r.s[d];
-          dst.v[d * n + j] = v;
-          dst.s2[d * n + j] = v + k.td1 * a1 + k.td2 * a2;
+          vf[d] = v;
+          vp[d] = v + k.td1 * a1 + k.td2 * a2;
           int li[3];
           lag_index(lat, r.lag, li);
           float x = (float)li[d] * (k.box / (float)lat.np) + r.s[d];
           x = x - k.box * floorf(x / k.box);
           if (x >= k.box) x -= k.box;
-          dst.s1[d * n + j] = x;
+          xo[d] = x;
         }
       }
-      if constexpr (MODE == kGatherFinish) dst.lag[r.lag] = j;
+      if constexpr (MODE == kGatherFinish) {
+        // finish: s, v, x = (q + s) mod L and v_phys packed in three float4 per
+        // particle, in this step's tile order, and the slot of every Lagrangian index
+        // in dst.lag, for k_unsort
+        float4* o4 = reinterpret_cast<float4*>(dst.s);
+        o4[j] = make_float4(r.s[0], r.s[1], r.s[2], vf[0]);
+        o4[n + j] = make_float4(vf[1], vf[2], xo[0], xo[1]);
+        o4[2 * n + j] = make_float4(xo[2], vp[0], vp[1], vp[2]);
+        dst.lag[r.lag] = j;
+      }
     }
     if constexpr (MODE == kGatherKickDrift) {
       int bin = 0;
@@ -791,7 +824,7 @@ Bins make_bins(int nm, int tz_max) {
   b.tx = kTX;
   b.ty = kTY;
   b.tz = 8;
-  while (b.tz < tz_max && b.tz < 32 && nm % (2 * b.tz) == 0) b.tz *= 2;
+  while (b.tz < tz_max && b.tz < 64 && nm % (2 * b.tz) == 0) b.tz *= 2;
   b.nbx = nm / b.tx;
   b.nby = nm / b.ty;
   b.nbz = nm / b.tz;
@@ -843,6 +876,7 @@ static unsigned tile_blocks(const Bins& b) { return (unsigned)((b.nbins + kXcds 
     case 8: { constexpr int TZ = 8; CALL; break; }   \
     case 16: { constexpr int TZ = 16; CALL; break; } \
     case 32: { constexpr int TZ = 32; CALL; break; } \
+    case 64: { constexpr int TZ = 64; CALL; break; } \
     default: return hipErrorInvalidValue;            \
   }
 
@@ -873,11 +907,11 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
                           hipStream_t st, const float* weight, const int* lag) {
   if (weight)
-    COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float>), dim3(tile_blocks(b)), dim3(kPartThreads),
+    COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float>), dim3(tile_blocks(b)), dim3(TileDims<TZ>::TT),
                                               0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass, weight))
   else
     COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long>), dim3(tile_blocks(b)),
-                                              dim3(kPartThreads), 0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass,
+                                              dim3(TileDims<TZ>::TT), 0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass,
                                               weight))
   return hipGetLastError();
 }
@@ -885,7 +919,7 @@ hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, fl
 template <int TZ>
 static void gather_tz(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
                       hipStream_t st) {
-  const dim3 grid(tile_blocks(b)), block(kPartThreads);
+  const dim3 grid(tile_blocks(b)), block(TileDims<TZ>::TT);
   if (mode == kGatherForce)
     hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherForce, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a, k,
                        bb.key_rank, bb.count_next);
@@ -910,7 +944,7 @@ hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_
 template <int TZ>
 static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                              GatherArgs a, KickArgs k, hipStream_t st) {
-  const dim3 grid(tile_blocks(b)), block(kPartThreads);
+  const dim3 grid(tile_blocks(b)), block(TileDims<TZ>::TT);
   if (mode == kGatherKickDrift)
     hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, src, dst, bb.idx,
                        bb.offset, a, k, bb.key_rank, bb.count_next);
@@ -923,15 +957,18 @@ hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedStat
                                 GatherArgs a, KickArgs k, hipStream_t st) {
   if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
   if (!dst.s || !dst.v || !dst.s1 || !dst.s2 || !dst.lag) return hipErrorInvalidValue;
+  if (mode == kGatherFinish && (reinterpret_cast<uintptr_t>(dst.s) % 16 != 0 || dst.v != dst.s + 3 * lat.npart ||
+                                dst.s1 != dst.s + 6 * lat.npart || dst.s2 != dst.s + 9 * lat.npart))
+    return hipErrorInvalidValue;   // the packed output needs one aligned block
   COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, src, dst, bb, mode, a, k, st));
   return hipGetLastError();
 }
 
-// Lagrangian order from the finish output: element p of each output takes slot
-// inv[p] of its tile-ordered copy (s, v, x, v_phys in w.s, w.v, w.s1, w.s2).
-// A block covers a 4 x 4 x 16 block of the Lagrangian grid (when np allows), whose
-// particles sit in a few neighbouring tiles, so its scattered reads stay local; its
-// writes are runs of 16 consecutive elements.
+// Lagrangian order from the finish output: particle p takes slot inv[p] of the
+// packed tile-ordered copy (three float4 per slot: s, v, x, v_phys).  A block covers a
+// 4 x 4 x 16 block of the Lagrangian grid (when np allows), whose particles sit in a
+// few neighbouring tiles, so its scattered 16-byte reads stay local; its writes are
+// runs of 16 consecutive elements.
 __global__ __launch_bounds__(kPartThreads) void k_unsort(int np, long n, SortedState w, GatherArgs g) {
   long p;
   if (np % 16 == 0) {
@@ -945,14 +982,20 @@ __global__ __launch_bounds__(kPartThreads) void k_unsort(int np, long n, SortedS
   }
   if (p >= n) return;
   const long j = w.lag[p];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const long o = d * n;
-    g.s[o + p] = w.s[o + j];
-    g.v[o + p] = w.v[o + j];
-    g.out_a[o + p] = w.s1[o + j];
-    g.out_b[o + p] = w.s2[o + j];
-  }
+  const float4* o4 = reinterpret_cast<const float4*>(w.s);
+  const float4 a = o4[j], b = o4[n + j], c = o4[2 * n + j];
+  g.s[p] = a.x;
+  g.s[n + p] = a.y;
+  g.s[2 * n + p] = a.z;
+  g.v[p] = a.w;
+  g.v[n + p] = b.x;
+  g.v[2 * n + p] = b.y;
+  g.out_a[p] = b.z;
+  g.out_a[n + p] = b.w;
+  g.out_a[2 * n + p] = c.x;
+  g.out_b[p] = c.y;
+  g.out_b[n + p] = c.z;
+  g.out_b[2 * n + p] = c.w;
 }
 
 hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t st) {
@@ -961,7 +1004,7 @@ hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t s
 }
 
 hipError_t launch_grad_gather(Lattice lat, Bins b, BinBuffers bb, const float* s, AdjGatherArgs ga, hipStream_t st) {
-  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_grad_gather<TZ>, dim3(tile_blocks(b)), dim3(kPartThreads), 0, st, lat, b,
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_grad_gather<TZ>, dim3(tile_blocks(b)), dim3(TileDims<TZ>::TT), 0, st, lat, b,
                                             bb.idx, bb.offset, s, ga));
   return hipGetLastError();
 }

@@ -6,6 +6,8 @@ run at 32^3 / 64^3: positions within 1e-3 of the box (per component, periodic) a
 max relative P(k) error <= 1e-4 over bins 1..nm/2 of the final density (the
 targets stated for this method's FP32 implementation).
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -125,6 +127,42 @@ def test_step_by_step_equals_run():
         # the deposit's FP32 atomics make the low bits order dependent
         assert rel_l2(host(x2), host(x1)) < 1e-5
         assert rel_l2(host(v2), host(v1)) < 1e-4
+
+
+@functools.lru_cache(maxsize=1)
+def _oracle_run_64_128():
+    cfg = cola.Config(np=64, nm=128)
+    w = inputs.white_noise(64, 21)
+    rx, rv, _ = ocola.run(w.astype(np.float64), _ocfg(cfg))
+    return cfg, w, rx.reshape(3, -1).numpy(), rv.reshape(3, -1).numpy()
+
+
+@pytest.mark.parametrize("depth", [8, 16, 32, 64])
+def test_bin_depths_agree_with_oracle(depth):
+    """Every tile depth of the deposit / gather bins (8 x 8 x depth cells; 256
+    threads per tile block below 64, 512 at 64) gives the same run: 64^3 particles
+    on a 128^3 mesh against the FP64 oracle, positions within 1e-3 of the box."""
+    cfg, w, rx, rv = _oracle_run_64_128()
+    announce(f"run 64/128 depth {depth}")
+    with cola.Plan(cfg) as plan:
+        plan.set_bin_depth(depth)
+        assert plan.get_tuning()[2] == depth
+        ws = plan.workspace()
+        p = cola.Particles.empty(64)
+        x = torch.empty((3, 64**3), dtype=torch.float32, device="cuda")
+        v = torch.empty_like(x)
+        plan.run(dev(w), p, x, v, ws)
+        x, v = host(x), host(v)
+    assert periodic_max_err(x, rx, cfg.box) < 1e-3 * cfg.box
+    assert rel_l2(v, rv) < 1e-4
+
+
+def test_bin_depth_rejects_invalid():
+    with cola.Plan(cola.Config(np=16, nm=48)) as plan:
+        with pytest.raises(cola.ColaError):
+            plan.set_bin_depth(12)
+        with pytest.raises(cola.ColaError):
+            plan.set_bin_depth(32)   # does not divide 48
 
 
 def test_full_size_run_properties():
