@@ -109,9 +109,10 @@ hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t s
 hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
 // Tile deposit: each tile accumulates its own particles and the boundary classes of
 // its lower neighbours that reach into it, then writes its cells with plain stores.
-// rho needs no clearing.  bb.idx lists slots of s by key; lag (optional) gives a
-// slot's Lagrangian index (the slot itself when null).  weight (optional, [np^3] by
-// Lagrangian index): the particle carries mass * weight.
+// rho needs no clearing.  bb.idx lists slots of s by key.  With lag, s is a packed
+// state (SortedState) and lag gives a slot's Lagrangian index; without, s is SoA
+// [3][np^3] in Lagrangian order.  weight (optional, [np^3] by Lagrangian index): the
+// particle carries mass * weight.
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
                           hipStream_t st, const float* weight = nullptr, const int* lag = nullptr);
 
@@ -145,7 +146,10 @@ hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_
                          hipStream_t st);
 
 // Particle state ordered by tile (slot j), with each particle's Lagrangian index.
-// lag == nullptr means slot = Lagrangian index (the caller's arrays).
+// lag == nullptr: the caller's SoA arrays s, v, s1, s2 ([3][n], slot = Lagrangian
+// index).  lag != nullptr: a packed state, s pointing at 12 n floats (16-byte
+// aligned) read as float4[3][n] = (s.x s.y s.z v.x), (v.y v.z s1.x s1.y),
+// (s1.z s2.x s2.y s2.z); v, s1, s2 are unused.
 struct SortedState {
   float* s;
   float* v;
@@ -154,12 +158,11 @@ struct SortedState {
   int* lag;
 };
 // Gather + kick over the tile lists bb.idx (slots of src).  kGatherKickDrift writes
-// the kicked and drifted record of list position j to slot j of dst (ordered by this
-// step's tiles) and bins it for the next step (bb.count_next, bb.key_rank by dst slot);
-// kGatherFinish packs the final s, v, x and v_phys of slot j into three float4 at
-// float4 index j, n + j, 2n + j from dst.s (the 12 n floats dst.s .. dst.s2 are one
-// contiguous, 16-byte aligned block) and sets dst.lag[Lagrangian index] = j, for
-// launch_unsort.
+// the kicked and drifted record of list position j to slot j of the packed dst
+// (ordered by this step's tiles) and bins it for the next step (bb.count_next,
+// bb.key_rank by dst slot); kGatherFinish packs the final s, v, x and v_phys of slot j
+// into float4 j, n + j, 2n + j of dst.s (a packed block) and sets
+// dst.lag[Lagrangian index] = j, for launch_unsort.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st);
 // Lagrangian order from a kGatherFinish output w: a.s, a.v, a.out_a, a.out_b take

@@ -330,29 +330,36 @@ __device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom
 template <int TZ, int NF>
 __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const float* const* f, float* tile) {
   using D = TileDims<TZ>;
-  constexpr int NS = (kTX + 1) * D::EY * TZ;   // staged cells
-  constexpr int IT = (NS + D::TT - 1) / D::TT;
-  float v[NF][IT];
+  constexpr int RQ = TZ / 4;                   // float4 per staged row
+  constexpr int NQ = (kTX + 1) * D::EY * RQ;   // staged float4
+  constexpr int IT = (NQ + D::TT - 1) / D::TT;
+  float4 v[NF][IT];
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     const int i = threadIdx.x + k * D::TT;
-    const int ii = i < NS ? i : NS - 1;
-    const int z = ii % TZ, r = ii / TZ;
+    const int ii = i < NQ ? i : NQ - 1;
+    const int zq = ii % RQ, r = ii / RQ;
     const int y = r % D::EY, x = r / D::EY;
     int gx = t.lo[0] + x, gy = t.lo[1] + y;
     gx -= (gx >= nm) ? nm : 0;
     gy -= (gy >= nm) ? nm : 0;
-    const long gi = ((long)gx * nm + gy) * nm + t.lo[2] + z;
+    const long gi = ((long)gx * nm + gy) * nm + t.lo[2] + 4 * zq;   // 16-byte aligned: nm, lo[2] are multiples of 8
 #pragma unroll
-    for (int c = 0; c < NF; ++c) v[c][k] = f[c][gi];
+    for (int c = 0; c < NF; ++c) v[c][k] = *reinterpret_cast<const float4*>(f[c] + gi);
   }
 #pragma unroll
   for (int k = 0; k < IT; ++k) {
     const int i = threadIdx.x + k * D::TT;
-    if (i < NS) {
-      const int z = i % TZ, r = i / TZ;
+    if (i < NQ) {
+      const int zq = i % RQ, r = i / RQ;
+      float* row = tile + r * D::EZ + 4 * zq;
 #pragma unroll
-      for (int c = 0; c < NF; ++c) tile[c * D::EXT + r * D::EZ + z] = v[c][k];
+      for (int c = 0; c < NF; ++c) {
+        row[c * D::EXT] = v[c][k].x;
+        row[c * D::EXT + 1] = v[c][k].y;
+        row[c * D::EXT + 2] = v[c][k].z;
+        row[c * D::EXT + 3] = v[c][k].w;
+      }
     }
   }
 }
@@ -380,8 +387,9 @@ __device__ __forceinline__ float corner_value(const float* tile_field, const flo
 // tile (accumulator ACC as above) and the tile's cells are then stored.
 //   ACC = unsigned long long: fixed-point sums (mass deposits); float: FP32 atomics
 //   (weighted deposits, whose weights have no bounded scale).
-// idx holds slots of s; lag (optional) maps a slot to its Lagrangian index (the slot
-// itself when null); weight is indexed by Lagrangian index.
+// idx holds slots of s; with lag (optional) s is a packed state (positions in the
+// first float4 of each slot) and lag maps a slot to its Lagrangian index; without,
+// s is SoA [3][np^3] in Lagrangian order.  weight is indexed by Lagrangian index.
 constexpr int kDepRanges = 20;
 
 template <int TZ, class ACC>
@@ -466,9 +474,17 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
       for (int q = 1; q < kDepRanges; ++q) r += (rpre[q] <= ii) ? 1 : 0;
       msk[u] = rmask[r];
       const unsigned slot = in[u] ? (unsigned)idx[rbeg[r] + ii - rpre[r]] : 0u;
-      lg[u] = lag ? (unsigned)lag[slot] : slot;
+      if (lag) {   // packed state: positions in the first float4 of the slot
+        lg[u] = (unsigned)lag[slot];
+        const float4 a = reinterpret_cast<const float4*>(s)[slot];
+        sv[u][0] = a.x;
+        sv[u][1] = a.y;
+        sv[u][2] = a.z;
+      } else {
+        lg[u] = slot;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) sv[u][d] = s[d * lat.npart + slot];
+        for (int d = 0; d < 3; ++d) sv[u][d] = s[d * lat.npart + slot];
+      }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -668,14 +684,28 @@ struct SortedRecord {
   float s[3], v[3], s1[3], s2[3];
 };
 
+// A packed state (lag != nullptr) holds slot j as three float4 in s viewed as
+// float4[3][n]: (s.x s.y s.z v.x), (v.y v.z s1.x s1.y), (s1.z s2.x s2.y s2.z), so an
+// indirect read of one particle touches 4 cache lines rather than 13.  The caller's
+// arrays (lag == nullptr) are SoA [3][n] in Lagrangian order.
 __device__ __forceinline__ void load_record(const SortedState& st, long n, int j, SortedRecord& r) {
-  r.lag = st.lag ? (unsigned)st.lag[j] : (unsigned)j;
+  if (st.lag) {
+    const float4* q = reinterpret_cast<const float4*>(st.s);
+    const float4 a = q[j], b = q[n + j], c = q[2 * n + j];
+    r.lag = (unsigned)st.lag[j];
+    r.s[0] = a.x; r.s[1] = a.y; r.s[2] = a.z;
+    r.v[0] = a.w; r.v[1] = b.x; r.v[2] = b.y;
+    r.s1[0] = b.z; r.s1[1] = b.w; r.s1[2] = c.x;
+    r.s2[0] = c.y; r.s2[1] = c.z; r.s2[2] = c.w;
+  } else {
+    r.lag = (unsigned)j;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    r.s[d] = st.s[d * n + j];
-    r.v[d] = st.v[d * n + j];
-    r.s1[d] = st.s1[d * n + j];
-    r.s2[d] = st.s2[d * n + j];
+    for (int d = 0; d < 3; ++d) {
+      r.s[d] = st.s[d * n + j];
+      r.v[d] = st.v[d * n + j];
+      r.s1[d] = st.s1[d * n + j];
+      r.s2[d] = st.s2[d * n + j];
+    }
   }
 }
 
@@ -729,17 +759,13 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
     float snew[3] = {r.s[0], r.s[1], r.s[2]};
     float vf[3], vp[3], xo[3];
     if (in) {
-      if constexpr (MODE == kGatherKickDrift) dst.lag[j] = (int)r.lag;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const float a1 = r.s1[d], a2 = r.s2[d];
         const float v = r.v[d] + k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
         if constexpr (MODE == kGatherKickDrift) {
           snew[d] = r.s[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
-          dst.s[d * n + j] = snew[d];
-          dst.v[d * n + j] = v;
-          dst.s1[d * n + j] = a1;
-          dst.s2[d * n + j] = a2;
+          vf[d] = v;
         } else {
           vf[d] = v;
           vp[d] = v + k.td1 * a1 + k.td2 * a2;
@@ -750,6 +776,13 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
           if (x >= k.box) x -= k.box;
           xo[d] = x;
         }
+      }
+      if constexpr (MODE == kGatherKickDrift) {
+        float4* q = reinterpret_cast<float4*>(dst.s);
+        q[j] = make_float4(snew[0], snew[1], snew[2], vf[0]);
+        q[n + j] = make_float4(vf[1], vf[2], r.s1[0], r.s1[1]);
+        q[2 * n + j] = make_float4(r.s1[2], r.s2[0], r.s2[1], r.s2[2]);
+        dst.lag[j] = (int)r.lag;
       }
       if constexpr (MODE == kGatherFinish) {
         // finish: s, v, x = (q + s) mod L and v_phys packed in three float4 per
@@ -956,10 +989,9 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st) {
   if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
-  if (!dst.s || !dst.v || !dst.s1 || !dst.s2 || !dst.lag) return hipErrorInvalidValue;
-  if (mode == kGatherFinish && (reinterpret_cast<uintptr_t>(dst.s) % 16 != 0 || dst.v != dst.s + 3 * lat.npart ||
-                                dst.s1 != dst.s + 6 * lat.npart || dst.s2 != dst.s + 9 * lat.npart))
-    return hipErrorInvalidValue;   // the packed output needs one aligned block
+  // dst is always packed: 12 n floats from dst.s, 16-byte aligned, and n ints of lag
+  if (!dst.s || !dst.lag || reinterpret_cast<uintptr_t>(dst.s) % 16 != 0) return hipErrorInvalidValue;
+  if (src.lag && reinterpret_cast<uintptr_t>(src.s) % 16 != 0) return hipErrorInvalidValue;
   COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, src, dst, bb, mode, a, k, st));
   return hipGetLastError();
 }
