@@ -98,8 +98,9 @@ struct BinBuffers {
   int* part;         // scan chunk sums
   long count_len;
 };
-// Tile depth: the largest of 8, 16, 32, 64 (<= tz_max) dividing nm.
-Bins make_bins(int nm, int tz_max = 32);
+// Tile depth: the largest of 8, 16, 32, 64 (<= tz_max) dividing nm (64 by default:
+// deeper tiles stage fewer halo cells per particle).
+Bins make_bins(int nm, int tz_max = 64);
 size_t bin_workspace_bytes(long npart, const Bins& b);
 BinBuffers carve_bins(void* base, long npart, const Bins& b);
 
