@@ -50,8 +50,8 @@ def stage_bytes(np_side: int, nm: int) -> dict:
         "fft_z_fwd": 4 * R + 8 * C,
         "fft_y_fwd": 16 * C,
         "fft_x_poisson": 8 * C + 24 * C,
-        "fft_y_inv": 48 * C,
-        "fft_z_inv": 24 * C + 12 * R,
+        "fft_y_inv": 16 * C,            # one force field per launch
+        "fft_z_inv": 8 * C + 4 * R,     # one force field per launch
         "gather_kick_drift": 12 * R + 72 * P,
         "gather_finish": 12 * R + 48 * P + 36 * P,
         "fill": 0,

@@ -176,11 +176,12 @@ Lattice lattice(cola_plan p) {
 // Forward y pass (in place) over nf fields of an n^3 half-spectrum layout.
 int width_for(cola_plan p, int n, int pass) { return n == p->cfg.nm ? p->fft_width[pass] : 0; }
 
-int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const float2* tw, hipStream_t st) {
+int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const float2* tw, hipStream_t st,
+          int reverse = 0) {
   const long h = n / 2;
   const int w = width_for(p, n, 0);
-  return hip_status(
-      traced(p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, w, st); }));
+  return hip_status(traced(
+      p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, w, st, reverse); }));
 }
 
 // Workspace: three real nm^3 meshes, then the binning buffers.
@@ -245,7 +246,10 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   const float2* tw = p->d_tw_nm;
   COLA_HIP(traced(p, kStZFwd, st,
                   [&] { return launch_zfwd(n, g0, reinterpret_cast<float2*>(g0), (long)n * n, tw, st); }));
-  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g0}), 1, tw, st));
+  // The y pass walks the rows the z pass wrote last first, and each force field goes
+  // through its y and z inverse passes back to back (the z pass again walking
+  // backwards), so those passes start on data still held by the memory-side cache.
+  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g0}), 1, tw, st, 1));
   const double kf = 2.0 * M_PI / p->cfg.box;
   MulArgs m{};
   m.c = (float)(1.5 * p->cfg.omega_m * a / (kf * (double)r));
@@ -253,12 +257,15 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
     return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(g0), fields({g0, g1, g2}), 3, m, tw,
                        p->fft_width[1], st);
   }));
-  COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0, g1, g2}), 3, tw, st));
   EpiArgs e{};
   e.scale = 1.0f;
-  COLA_HIP(traced(p, kStZInv, st, [&] {
-    return launch_zinv(n, fields({g0, g1, g2}), fields({g0, g1, g2}), 3, (long)n * n, tw, kEpiStore, e, st);
-  }));
+  e.reverse = 1;
+  for (float* g : {g2, g1, g0}) {
+    COLA_TRY(ypass(p, kStYInv, n, 1, fields({g}), 1, tw, st));
+    COLA_HIP(traced(p, kStZInv, st, [&] {
+      return launch_zinv(n, fields({g}), fields({g}), 1, (long)n * n, tw, kEpiStore, e, st);
+    }));
+  }
   return COLA_OK;
 }
 

@@ -39,6 +39,7 @@ struct EpiArgs {
   float* s;
   float* v;
   long comp_stride;
+  int reverse;        // rows from the last block to the first (memory-side cache reuse)
 };
 
 bool fft_size_supported(int n);
@@ -58,9 +59,10 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 // Strided column pass (length n along inner_stride) over tiles of contiguous columns.
 // Tiles: outer index o in [0, n_outer) at outer_stride; columns [0, ncols) contiguous.
 // width: columns per tile (4, 8 or 16; 0 picks the default for n).
+// reverse: blocks take the tiles from the last to the first.
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, int n_outer,
                       long outer_stride, long inner_stride, int ncols, const float2* tw, int width,
-                      hipStream_t st);
+                      hipStream_t st, int reverse = 0);
 // x pass with the k-space multiplier: forward x transform of `in`, multiply, inverse
 // x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row.
 // kMulGrad requires nout = 3, kMulLpt1 1..9.

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(ZPencil<N>::T) void k_zinv(FieldPtrs in, FieldPtrs 
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
   const int f = blockIdx.y;
-  const long row0 = (long)blockIdx.x * P::NT;
+  const long row0 = (long)(e.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x) * P::NT;
   float2 q[P::UB][P::R1];
   P::load_b(q, in.p[f] + row0 * M, M);
   load_twiddles(stw, tw, N);
@@ -205,16 +205,20 @@ __global__ __launch_bounds__(ZHPencil<N>::T) void k_zinv_hess(FieldPtrs in, floa
 // ---------------------------------------------------------------------------------
 // Strided column pass: tile = n elements along inner_stride x B contiguous columns.
 // ---------------------------------------------------------------------------------
+// reverse: blocks walk the tiles from the last to the first, so a pass that follows
+// one which wrote the same array in ascending order starts on the data written last
+// (still in the memory-side cache).
 template <int N, int B, int S>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, FieldPtrs out, long outer_stride,
                                                                 long inner_stride, int ntiles_c,
-                                                                const float2* __restrict__ tw) {
+                                                                const float2* __restrict__ tw, int reverse) {
   using P = Pencil<N, B, false>;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
   const int f = blockIdx.y;
-  const int tc = blockIdx.x % ntiles_c;
-  const long o = blockIdx.x / ntiles_c;
+  const unsigned blk = reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x;
+  const int tc = blk % ntiles_c;
+  const long o = blk / ntiles_c;
   const long origin = o * outer_stride + (long)tc * B;
   float2 a[P::R2];
   P::load_a(a, in.p[f] + origin, inner_stride);
@@ -422,16 +426,18 @@ static hipError_t zinv_hess_t(FieldPtrs in, float* out, long nrows, const float2
 
 template <int N, int B>
 static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                         long inner_stride, int ncols, const float2* tw, hipStream_t st) {
+                         long inner_stride, int ncols, const float2* tw, int reverse, hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
     if (ncols % B) return hipErrorInvalidValue;
     constexpr int T = Pencil<N, B, false>::T;
     const int ntc = ncols / B;
     dim3 grid((unsigned)((long)n_outer * ntc), nf);
     if (dir < 0)
-      hipLaunchKernelGGL((k_col<N, B, -1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw);
+      hipLaunchKernelGGL((k_col<N, B, -1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw,
+                         reverse);
     else
-      hipLaunchKernelGGL((k_col<N, B, 1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw);
+      hipLaunchKernelGGL((k_col<N, B, 1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw,
+                         reverse);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -440,11 +446,11 @@ static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_out
 
 template <int N>
 static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                        long inner_stride, int ncols, const float2* tw, int width, hipStream_t st) {
+                        long inner_stride, int ncols, const float2* tw, int width, int reverse, hipStream_t st) {
   switch (width ? width : col_width_default(N)) {
-    case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
-    case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
-    case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, st);
+    case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -557,11 +563,11 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 }
 
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                      long inner_stride, int ncols, const float2* tw, int width, hipStream_t st) {
+                      long inner_stride, int ncols, const float2* tw, int width, hipStream_t st, int reverse) {
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, st);
+    return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:
