@@ -12,12 +12,13 @@ It is a plain, slow, obviously-correct statement of what the method computes:
 
 * ``cosmology`` -- background Q(a), growth factors D1, D2 and their T, T^2
   derivatives, the BBKS spectrum and its sigma8 normalisation, and the COLA
-  kick/drift coefficients of eq. (KDKALC) on the time grid of eq. (ALCtimestep).
+  kick/drift coefficients of eq. (KDKALC) on the time grid of eq. (ALCtimestep),
+  and of the variants eq. (KDKALCstd) and eq. (KDKStd), steps uniform in a or log a.
 * ``lpt``       -- second-order LPT displacement fields s1, s2 from a Gaussian field.
 * ``pm``        -- cloud-in-cell deposit, k-space Poisson solve with spectral
   gradient, cloud-in-cell gather: the force -(3/2) Om a d d^-2 delta of eq. (eom).
 * ``cola``      -- the COLA time evolution L+ (prod K D K) L- of eqs. (ALCtimestep),
-  (Lops) and (KDKALC).
+  (Lops) and (KDKALC), or the plain PM leapfrog of eq. (KDKStd).
 * ``power``     -- the shell-averaged power spectrum used to compare final densities.
 * ``philox``    -- Philox4x32-10 counter-based generator and Box-Muller normals.
 

@@ -16,6 +16,12 @@ the sum of the two; one force evaluation per step plus one at a_n.
 Kick (KDKALC):  v += alpha * (F(s, a_c) - T^2[D1](a_c) s1 - T^2[D2](a_c) s2)
 Drift (KDKALC): s += beta * v + (D1(a_f) - D1(a_i)) s1 + (D2(a_f) - D2(a_i)) s2
 L+- (Lops):     v +-= T[D1](a) s1 + T[D2](a) s2
+
+Config.scheme "standard" uses the same operators with the factors of eq.
+(KDKALCstd) (taken from the step table).  Config.scheme "pm" is the plain PM
+leapfrog of eq. (KDKStd): the operators above with s1 = s2 = 0, so that L+- do
+nothing, the state is the full displacement s and the full velocity v = T[s], and
+the kick adds the plain force; the particles still start on the 2LPT trajectory.
 """
 from __future__ import annotations
 
@@ -37,11 +43,17 @@ class State:
     s2: torch.Tensor
 
 
-def initial_state(s1, s2, table: cosmo.StepTable) -> State:
-    """2LPT position and velocity at a_0, then L-(a_0): v_res(a_0) = 0 (eq. Lops)."""
+def initial_state(s1, s2, table: cosmo.StepTable, lpt_frame: bool = True) -> State:
+    """2LPT position and velocity at a_0, then L-(a_0): v_res(a_0) = 0 (eq. Lops).
+
+    lpt_frame False (eq. KDKStd): the operators act with s1 = s2 = 0, so the state
+    keeps the 2LPT velocity and carries zero LPT fields.
+    """
     g = table.grow
     s = g["D1"][0] * s1 + g["D2"][0] * s2
     v = g["TD1"][0] * s1 + g["TD2"][0] * s2          # T[s] of the 2LPT trajectory
+    if not lpt_frame:
+        return State(s=s, v=v, s1=torch.zeros_like(s1), s2=torch.zeros_like(s2))
     v = v - (g["TD1"][0] * s1 + g["TD2"][0] * s2)     # L-(a_0)
     return State(s=s, v=v, s1=s1, s2=s2)
 
@@ -80,7 +92,7 @@ def evolve(s1, s2, cfg: cosmo.Config, table: cosmo.StepTable | None = None,
            keep_states: bool = False):
     """Full evolution from given LPT fields.  Returns (x, v_phys, s[, states])."""
     table = cosmo.step_table(cfg) if table is None else table
-    st = initial_state(s1, s2, table)
+    st = initial_state(s1, s2, table, lpt_frame=cfg.scheme != "pm")
     states = [st]
     for i in range(cfg.n_steps):
         st = step(st, i, table, cfg)

@@ -18,6 +18,19 @@ Paper passages followed:
 * eq. (ALCtimestep) and the text after it: timesteps uniform in a, with
   a_{i+1/2} the arithmetic midpoint (Appendix A.2).  Consecutive half-kicks that
   share a_c = a_i are merged into one kick (exact: same force, factors add).
+* Variants (``Config.scheme``): eq. (KDKALCstd), the standard COLA discretisation,
+  kick factor int (a/a_c)/Q da and drift factor int 1/Q da; eq. (KDKStd), the plain
+  PM leapfrog, which is eq. (KDKALCstd) with s1 = s2 = 0 (Appendix A.3.1).  Its
+  kick carries -(3/2) Om d d^-2 delta without the factor a_c, so with the force
+  F = -(3/2) Om a_c d d^-2 delta the factor is again int (a/a_c)/Q da.
+  ``Config.log_a_steps``: a_i uniform in log a (Appendix A.2), midpoints still
+  arithmetic (the choice stated there for small steps).
+
+Readings of the variants: eq. (KDKALCstd) is printed with a minus sign in front of
+the kick integral while the bracket it multiplies is already the acceleration; read
+with a plus sign, which is what setting s1 = s2 = 0 must give to recover eq.
+(KDKStd), as the text after it states, and what eq. (KDKALC) has.  eq. (KDKStd)
+prints d_x d_x^2; read d_x d_x^-2 as in eq. (eom).
 
 Readings where the paper is silent: flat-or-curved FRW with matter, curvature and
 Lambda and no radiation, E^2 = Om a^-3 + Ok a^-2 + OL; BBKS transfer function with
@@ -48,6 +61,8 @@ class Config:
     a_final: float = 1.0
     n_steps: int = 10
     n_lpt: float = -2.5
+    scheme: str = "modified"   # "modified" eq. (KDKALC), "standard" eq. (KDKALCstd), "pm" eq. (KDKStd)
+    log_a_steps: bool = False  # a_i uniform in log a instead of in a
 
     @property
     def omega_k(self) -> float:
@@ -117,9 +132,14 @@ def growth(a, cfg: Config) -> dict:
 # Time grid and COLA kick / drift coefficients, eq. (KDKALC) and eq. (ALCtimestep).
 # ----------------------------------------------------------------------------------
 def time_grid(cfg: Config):
-    """a_i uniform in a (i = 0..n) and the midpoints a_{i+1/2} (i = 0..n-1)."""
+    """a_i (i = 0..n), uniform in a or in log a, and the midpoints a_{i+1/2} (i = 0..n-1)."""
     n = cfg.n_steps
-    a = cfg.a_init + (cfg.a_final - cfg.a_init) * np.arange(n + 1, dtype=np.float64) / n
+    t = np.arange(n + 1, dtype=np.float64) / n
+    if cfg.log_a_steps:
+        a = cfg.a_init * (cfg.a_final / cfg.a_init) ** t
+    else:
+        a = cfg.a_init + (cfg.a_final - cfg.a_init) * t
+    a[-1] = cfg.a_final
     return a, 0.5 * (a[:-1] + a[1:])
 
 
@@ -146,6 +166,18 @@ def drift_factor(a_i, a_f, a_c, cfg: Config) -> float:
     return val / float(u_of_a(a_c, cfg))
 
 
+def kick_factor_std(a_i, a_f, a_c, cfg: Config) -> float:
+    """Standard kick factor, eqs. (KDKALCstd) and (KDKStd): int_{a_i}^{a_f} (a/a_c)/Q da."""
+    val, _ = quad(lambda x: float(x / q_of_a(x, cfg)), a_i, a_f, epsabs=0.0, epsrel=1e-13, limit=200)
+    return val / a_c
+
+
+def drift_factor_std(a_i, a_f, cfg: Config) -> float:
+    """Standard drift factor, eqs. (KDKALCstd) and (KDKStd): int_{a_i}^{a_f} 1/Q da."""
+    val, _ = quad(lambda x: float(1.0 / q_of_a(x, cfg)), a_i, a_f, epsabs=0.0, epsrel=1e-13, limit=200)
+    return val
+
+
 @dataclass
 class StepTable:
     a: np.ndarray            # a_0 .. a_n
@@ -158,12 +190,15 @@ class StepTable:
 
 
 def step_table(cfg: Config) -> StepTable:
-    """All per-step scalars of the COLA evolution (ALCtimestep) with (KDKALC).
+    """All per-step scalars of the evolution (ALCtimestep) with the scheme's factors.
 
     Step i (0 <= i < n) = kick at a_i over [a_{i-1/2}, a_{i+1/2}] (over
     [a_0, a_{1/2}] for i = 0) followed by the drift over [a_i, a_{i+1}] with
     a_c = a_{i+1/2}.  The closing half-kick over [a_{n-1/2}, a_n] uses alpha[n].
     """
+    if cfg.scheme not in ("modified", "standard", "pm"):
+        raise ValueError(f"unknown scheme {cfg.scheme!r}")
+    std = cfg.scheme != "modified"
     a, am = time_grid(cfg)
     n = cfg.n_steps
     alpha = np.empty(n + 1)
@@ -171,8 +206,9 @@ def step_table(cfg: Config) -> StepTable:
     for i in range(n + 1):
         lo = a[0] if i == 0 else am[i - 1]
         hi = a[n] if i == n else am[i]
-        alpha[i] = kick_factor(lo, hi, a[i], cfg)
-    beta = np.array([drift_factor(a[i], a[i + 1], am[i], cfg) for i in range(n)])
+        alpha[i] = kick_factor_std(lo, hi, a[i], cfg) if std else kick_factor(lo, hi, a[i], cfg)
+    beta = np.array([drift_factor_std(a[i], a[i + 1], cfg) if std else drift_factor(a[i], a[i + 1], am[i], cfg)
+                     for i in range(n)])
     g = growth(a, cfg)
     return StepTable(a=a, a_mid=am, alpha=alpha, beta=beta,
                      dD1=np.diff(g["D1"]), dD2=np.diff(g["D2"]), grow=g)

@@ -54,13 +54,27 @@ def test_workspace_size():
             assert 12 * np_side**3 < extra < 12 * np_side**3 + 0.4 * nm**3 * 4
 
 
+def _oracle_scheme(flags: int) -> dict:
+    """Oracle Config fields for the library's variant flags."""
+    out = {"log_a_steps": bool(flags & cola.COLA_FLAG_LOG_A_STEPS)}
+    if flags & cola.COLA_FLAG_NO_LPT_FRAME:
+        out["scheme"] = "pm"
+    elif flags & cola.COLA_FLAG_KDK_STD:
+        out["scheme"] = "standard"
+    return out
+
+
 @pytest.mark.parametrize("kw", [{}, {"n_steps": 3}, {"omega_m": 0.25, "omega_l": 0.75}, {"n_lpt": 1.5},
-                                {"omega_m": 0.3, "omega_l": 0.6}])
+                                {"omega_m": 0.3, "omega_l": 0.6},
+                                {"flags": cola.COLA_FLAG_KDK_STD},
+                                {"flags": cola.COLA_FLAG_NO_LPT_FRAME, "n_steps": 7},
+                                {"flags": cola.COLA_FLAG_LOG_A_STEPS},
+                                {"flags": cola.COLA_FLAG_KDK_STD | cola.COLA_FLAG_LOG_A_STEPS, "a_init": 0.02}])
 def test_host_step_table_matches_oracle(kw):
     cfg = cola.Config(**kw)
     with cola.Plan(cfg) as p:
         t = p.step_table()
-    ocfg = cosmo.Config(**{k: v for k, v in kw.items()})
+    ocfg = cosmo.Config(**{k: v for k, v in kw.items() if k != "flags"}, **_oracle_scheme(kw.get("flags", 0)))
     ot = cosmo.step_table(ocfg)
     g = ot.grow
     np.testing.assert_allclose(t["a"], ot.a, rtol=1e-14)

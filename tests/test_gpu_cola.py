@@ -23,9 +23,19 @@ pytestmark = pytest.mark.gpu
 
 
 def _ocfg(c: cola.Config) -> cosmo.Config:
+    scheme = "modified"
+    if c.flags & cola.COLA_FLAG_NO_LPT_FRAME:
+        scheme = "pm"
+    elif c.flags & cola.COLA_FLAG_KDK_STD:
+        scheme = "standard"
     return cosmo.Config(np_side=c.np, nm_side=c.nm, box=c.box, omega_m=c.omega_m, omega_l=c.omega_l, h=c.h,
                         n_s=c.n_s, sigma8=c.sigma8, a_init=c.a_init, a_final=c.a_final, n_steps=c.n_steps,
-                        n_lpt=c.n_lpt)
+                        n_lpt=c.n_lpt, scheme=scheme, log_a_steps=bool(c.flags & cola.COLA_FLAG_LOG_A_STEPS))
+
+
+_STD = cola.COLA_FLAG_KDK_STD
+_PM = cola.COLA_FLAG_NO_LPT_FRAME
+_LOG = cola.COLA_FLAG_LOG_A_STEPS
 
 
 def test_noise_matches_oracle_generator():
@@ -56,19 +66,37 @@ def test_2lpt_matches_oracle(np_side, nm, box):
     assert np.abs(v).max() == 0.0
 
 
-def test_single_step_matches_oracle():
-    cfg = cola.Config(np=32, nm=64)
+def test_2lpt_plain_pm_keeps_the_lpt_velocity():
+    # eq. (KDKStd): no L-(a_0); the state starts with the 2LPT velocity T[s](a_0).
+    cfg = cola.Config(np=32, nm=64, flags=_PM)
+    w = inputs.white_noise(32, 1301)
+    announce("init_2lpt np=32 plain PM")
+    with cola.Plan(cfg) as plan:
+        p = cola.Particles.empty(32)
+        plan.init_2lpt(dev(w), p, plan.workspace())
+        s, v = host(p.s), host(p.v)
+    oc = _ocfg(cfg)
+    rs1, rs2 = lpt.lpt_from_noise(w.astype(np.float64), oc)
+    st = ocola.initial_state(rs1, rs2, cosmo.step_table(oc), lpt_frame=False)
+    assert rel_l2(s, st.s.reshape(3, -1).numpy()) < 1e-5
+    assert rel_l2(v, st.v.reshape(3, -1).numpy()) < 1e-5
+
+
+@pytest.mark.parametrize("flags", [0, _STD, _PM | _LOG])
+def test_single_step_matches_oracle(flags):
+    cfg = cola.Config(np=32, nm=64, flags=flags)
     oc = _ocfg(cfg)
     table = cosmo.step_table(oc)
     w = inputs.white_noise(32, 7)
     rs1, rs2 = lpt.lpt_from_noise(w.astype(np.float64), oc)
-    st = ocola.initial_state(rs1, rs2, table)
+    st = ocola.initial_state(rs1, rs2, table, lpt_frame=oc.scheme != "pm")
     for _ in range(3):                        # evolve the oracle a little first
         st = ocola.step(st, _, table, oc)
     f32 = lambda t: dev(t.reshape(3, -1).numpy().astype(np.float32))
     with cola.Plan(cfg) as plan:
+        # the plain PM state carries zero LPT fields (the operators ignore them)
         p = cola.Particles(f32(st.s), f32(st.v), f32(st.s1), f32(st.s2))
-        announce("step 3")
+        announce(f"step 3 flags={flags}")
         plan.step(3, p, plan.workspace())
         s, v = host(p.s), host(p.v)
     ref = ocola.step(ocola.State(*(torch.from_numpy(x.reshape(3, 32, 32, 32)).double() for x in
@@ -108,8 +136,30 @@ def test_full_run_matches_oracle(seed):
     assert x.min() >= 0.0 and x.max() < cfg.box
 
 
-def test_step_by_step_equals_run():
-    cfg = cola.Config(np=16, nm=32)
+@pytest.mark.parametrize("flags", [_STD, _PM, _LOG, _STD | _LOG, _PM | _LOG])
+def test_variant_run_matches_oracle(flags):
+    # eqs. (KDKALCstd), (KDKStd) and steps uniform in log a (Appendix A.2), same bars
+    # as the default scheme.
+    cfg = cola.Config(np=32, nm=64, flags=flags)
+    oc = _ocfg(cfg)
+    w = inputs.white_noise(32, 1301)
+    announce(f"run 32/64 flags={flags}")
+    x, v, p = cola.run(cfg, dev(w))
+    x, v = host(x), host(v)
+    rx, rv, rs = ocola.run(w.astype(np.float64), oc)
+    rx = rx.reshape(3, -1).numpy()
+    err = periodic_max_err(x, rx, cfg.box)
+    assert err <= 1e-3 * cfg.box, err
+    assert rel_l2(v, rv.reshape(3, -1).numpy()) < 1e-4
+    pk_gpu, _ = power.power_of_positions(torch.from_numpy(x.astype(np.float64)), cfg.nm, cfg.box)
+    pk_orc, _ = power.power_of_positions(torch.from_numpy(rx), cfg.nm, cfg.box)
+    rel = (pk_gpu / pk_orc - 1.0).abs().max().item()
+    assert rel <= 1e-4, rel
+
+
+@pytest.mark.parametrize("flags", [0, _PM | _LOG])
+def test_step_by_step_equals_run(flags):
+    cfg = cola.Config(np=16, nm=32, flags=flags)
     w = dev(inputs.white_noise(16, 3))
     with cola.Plan(cfg) as plan:
         ws = plan.workspace()

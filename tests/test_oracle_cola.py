@@ -9,6 +9,9 @@
 * Zel'dovich motion of a 1D plane wave is exact before shell crossing: x = q +
   D1(a) s1; the deviation is the PM force error and falls with resolution.
 * Momentum: sum of v_res and of s_res stay zero.
+* Variants: the modified, standard (eq. KDKALCstd) and plain PM (eq. KDKStd)
+  schemes converge to one trajectory at second order; the standard COLA scheme
+  keeps linear growth exact with few steps, plain PM does not.
 * v_res(a_0) = 0 after L-(a_0) (eq. Lops).
 * 2LPT sign convention: the Eulerian density of x = q + D1 s1 + D2 s2 at second
   order reproduces the perturbation-theory kernel
@@ -69,6 +72,76 @@ def test_zeldovich_plane_wave_converges():
     d = [_zeldovich_deviation(n, 1) for n in (16, 32, 64)]
     assert d[0] / d[1] > 1.8 and d[1] / d[2] > 1.8
     assert d[2] < 0.02
+
+
+def _plane_wave_run(scheme, n_steps, log_a, n_p=16):
+    cfg = cosmo.Config(np_side=n_p, nm_side=n_p, scheme=scheme, n_steps=n_steps, log_a_steps=log_a)
+    q = lpt.lagrangian_grid(n_p, cfg.box)
+    k = 2 * math.pi / cfg.box
+    amp = 0.5 / k
+    s1 = torch.zeros(3, n_p, n_p, n_p, dtype=F64)
+    s1[0] = amp * torch.sin(k * q[0])
+    _, v, s = cola.evolve(s1, torch.zeros_like(s1), cfg)
+    return s, v, amp
+
+
+def test_all_schemes_converge_to_one_trajectory():
+    # eqs. (KDKALC), (KDKALCstd) and (KDKStd) discretise the same equation of
+    # motion T^2[s] = F(s, a) with the same mesh force, so with more steps each
+    # approaches one trajectory, at second order in the step, on either grid.
+    s_ref, v_ref, amp = _plane_wave_run("modified", 160, False)
+    vscale = v_ref.abs().max().item()
+    for scheme in ("pm", "standard", "modified"):
+        for log_a in (False, True):
+            errs = []
+            for n in (20, 80):
+                s, v, _ = _plane_wave_run(scheme, n, log_a)
+                errs.append(max((s - s_ref).abs().max().item() / amp, (v - v_ref).abs().max().item() / vscale))
+            assert errs[1] < 5e-4, (scheme, log_a, errs)
+            assert errs[0] / errs[1] > 6.0, (scheme, log_a, errs)
+
+
+def test_standard_cola_exact_in_linear_regime_and_pm_is_not():
+    # Both COLA discretisations take the linear growth from D1, D2 and leave only
+    # the (here vanishing) residual to the steps: 3 standard steps give the same
+    # lowest-shell growth as 10 modified steps, up to the PM force error.  The plain
+    # PM leapfrog (eq. KDKStd) integrates the growth itself and carries a step error;
+    # uniform in log a it does better than uniform in a (Appendix A.2).
+    d_mod = _linear_growth_deviation_cfg(32, 1)
+    d_std = _linear_growth_deviation_cfg(32, 1, scheme="standard", n_steps=3)
+    d_pm_a = _linear_growth_deviation_cfg(32, 1, scheme="pm", n_steps=10)
+    d_pm_log = _linear_growth_deviation_cfg(32, 1, scheme="pm", n_steps=10, log_a_steps=True)
+    assert abs(d_mod) < 0.04
+    assert abs(d_std - d_mod) < 0.01
+    assert abs(d_pm_a - d_mod) > 0.01
+    assert abs(d_pm_log - d_mod) < 0.5 * abs(d_pm_a - d_mod)
+
+
+def _linear_growth_deviation_cfg(n_p, ratio, seed=1301, **kw):
+    cfg = cosmo.Config(np_side=n_p, nm_side=ratio * n_p, **kw)
+    w = np.random.default_rng(seed).standard_normal(n_p**3)
+    amp = cosmo.power_amplitude(cfg) * 1e-8
+    s1, s2 = lpt.lpt_from_noise(w, cfg, amp)
+    tab = cosmo.step_table(cfg)
+    st0 = cola.initial_state(s1, s2, tab)
+    x, _, _ = cola.evolve(s1, s2, cfg, tab)
+    q = lpt.lagrangian_grid(n_p, cfg.box)
+    p0, _ = power.power_of_positions(q + st0.s, n_p, cfg.box)
+    p1, _ = power.power_of_positions(x, n_p, cfg.box)
+    return float(p1[0] / p0[0] / ((tab.grow["D1"][-1] / tab.grow["D1"][0]) ** 2) - 1.0)
+
+
+def test_pm_state_carries_the_full_velocity():
+    # eq. (KDKStd) is eq. (KDKALCstd) with s1 = s2 = 0: no L-, the state starts with
+    # the 2LPT velocity T[s](a_0) and its LPT fields are zero.
+    cfg = cosmo.Config(np_side=8, nm_side=8, scheme="pm")
+    w = np.random.default_rng(5).standard_normal(8**3)
+    s1, s2 = lpt.lpt_from_noise(w, cfg)
+    tab = cosmo.step_table(cfg)
+    st = cola.initial_state(s1, s2, tab, lpt_frame=False)
+    g = tab.grow
+    assert torch.equal(st.v, g["TD1"][0] * s1 + g["TD2"][0] * s2)
+    assert st.s1.abs().max().item() == 0.0 and st.s2.abs().max().item() == 0.0
 
 
 def test_momentum_and_initial_velocity():

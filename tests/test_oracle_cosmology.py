@@ -3,7 +3,8 @@
 Each check compares the oracle against something other than itself: closed forms
 of the Einstein-de Sitter case, the Heath integral for D1, the standard D2 fit,
 the toy-model exactness of the modified kick/drift (Appendix A.3.2, eq. toyKDK)
-integrated independently, and the constants the paper states.
+integrated independently, the exact cases and second-order convergence of the
+standard kick/drift (eqs. KDKStd, KDKALCstd), and the constants the paper states.
 """
 import numpy as np
 import pytest
@@ -123,6 +124,71 @@ def test_generic_force_converges_at_second_order():
         cfg = cosmo.Config(n_steps=n)
         s_num, v_num = _run_scalar_kdk(f, 0.0, cfg, cosmo.step_table(cfg))
         s_ex, v_ex = _exact_scalar(f, 0.0, cfg)
+        errs.append(abs(s_num - s_ex) / abs(s_ex))
+    assert 3.0 < errs[0] / errs[1] < 5.0
+    assert 3.0 < errs[1] / errs[2] < 5.0
+
+
+@pytest.mark.parametrize("ai,af,ac", [(0.1, 0.19, 0.145), (0.37, 0.64, 0.37), (0.5, 1.0, 1.0)])
+def test_standard_factors_eds_closed_forms(ai, af, ac):
+    # eqs. (KDKStd), (KDKALCstd) with Omega_m = 1, Q = a^(3/2):
+    # int 1/Q da = 2 (a_i^-1/2 - a_f^-1/2), int (a/a_c)/Q da = 2 (a_f^1/2 - a_i^1/2) / a_c.
+    assert cosmo.drift_factor_std(ai, af, EDS) == pytest.approx(2 * (ai**-0.5 - af**-0.5), rel=1e-12)
+    assert cosmo.kick_factor_std(ai, af, ac, EDS) == pytest.approx(2 * (af**0.5 - ai**0.5) / ac, rel=1e-12)
+
+
+def test_log_a_grid():
+    # Appendix A.2: steps uniform in log a (constant ratio), midpoints arithmetic.
+    cfg = cosmo.Config(log_a_steps=True, a_init=0.02, n_steps=7)
+    a, am = cosmo.time_grid(cfg)
+    np.testing.assert_allclose(a[1:] / a[:-1], (1.0 / 0.02) ** (1.0 / 7), rtol=1e-13)
+    assert a[0] == 0.02 and a[-1] == 1.0
+    np.testing.assert_allclose(am, 0.5 * (a[1:] + a[:-1]), rtol=1e-15)
+
+
+@pytest.mark.parametrize("scheme", ["standard", "pm"])
+@pytest.mark.parametrize("log_a", [False, True])
+def test_standard_merged_factors_tile_the_run(scheme, log_a):
+    # The merged kicks cover [a_0, a_n] once and the drifts [a_0, a_n] once, so in
+    # Einstein-de Sitter sum_i alpha_i a_i = 2 (a_n^1/2 - a_0^1/2) and
+    # sum_i beta_i = 2 (a_0^-1/2 - a_n^-1/2), for any grid.
+    cfg = cosmo.Config(omega_m=1.0, omega_l=0.0, scheme=scheme, log_a_steps=log_a, n_steps=6)
+    t = cosmo.step_table(cfg)
+    assert float(np.sum(t.alpha * t.a)) == pytest.approx(2 * (1.0 - 0.1**0.5), rel=1e-12)
+    assert float(np.sum(t.beta)) == pytest.approx(2 * (0.1**-0.5 - 1.0), rel=1e-12)
+
+
+def test_unknown_scheme_rejected():
+    with pytest.raises(ValueError):
+        cosmo.step_table(cosmo.Config(scheme="leapfrog"))
+
+
+@pytest.mark.parametrize("scheme", ["standard", "pm"])
+def test_standard_kick_exact_for_a_proportional_force(scheme):
+    # eq. (KDKStd): the kick holds d d^-2 delta fixed over its interval, so a force
+    # F(a) = c a (fixed d d^-2 delta) is integrated exactly: v_n = v_0 + c int a/Q da.
+    # A zero force leaves v fixed and the drift exact: s_n = v_0 int 1/Q da.
+    for log_a in (False, True):
+        cfg = cosmo.Config(scheme=scheme, log_a_steps=log_a, n_steps=4)
+        table = cosmo.step_table(cfg)
+        c, v0 = 0.61, 0.23
+        ia = quad(lambda x: x / float(cosmo.q_of_a(x, cfg)), 0.1, 1.0, epsabs=0, epsrel=1e-13)[0]
+        i1 = quad(lambda x: 1.0 / float(cosmo.q_of_a(x, cfg)), 0.1, 1.0, epsabs=0, epsrel=1e-13)[0]
+        _, v_num = _run_scalar_kdk(lambda a: c * a, v0, cfg, table)
+        assert v_num == pytest.approx(v0 + c * ia, rel=1e-12)
+        s_num, v_num = _run_scalar_kdk(lambda a: 0.0, v0, cfg, table)
+        assert v_num == v0
+        assert s_num == pytest.approx(v0 * i1, rel=1e-12)
+
+
+@pytest.mark.parametrize("log_a", [False, True])
+def test_standard_leapfrog_converges_at_second_order(log_a):
+    errs = []
+    f = lambda a: 0.8 * a**2 + 0.3
+    for n in (20, 40, 80):
+        cfg = cosmo.Config(n_steps=n, scheme="standard", log_a_steps=log_a)
+        s_num, _ = _run_scalar_kdk(f, 0.1, cfg, cosmo.step_table(cfg))
+        s_ex, _ = _exact_scalar(f, 0.1, cfg)
         errs.append(abs(s_num - s_ex) / abs(s_ex))
     assert 3.0 < errs[0] / errs[1] < 5.0
     assert 3.0 < errs[1] / errs[2] < 5.0
