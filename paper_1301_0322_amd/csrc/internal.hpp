@@ -90,6 +90,7 @@ struct Bins {
   int nbx, nby, nbz;
   long nbins;
   long nkeys;        // 8 nbins
+  int heavy_cap;     // crowded-tile list capacity (a multiple of 8, about nbins / 16)
 };
 struct BinBuffers {
   int2* key_rank;    // [npart] (key, rank within key)
@@ -98,8 +99,16 @@ struct BinBuffers {
   int* count_next;   // [count_len] counts for the next step, filled by a binning gather
   int* offset;       // [count_len] exclusive prefix sum, offset[nkeys] = npart
   int* part;         // scan chunk sums
+  int* heavy;        // [1 + heavy_cap] number of crowded tiles, then their indices
   long count_len;
+  long npart;
 };
+// A tile is crowded when its own classes hold more than ceil(npart / heavy_cap)
+// particles; fewer than heavy_cap tiles can be.  The scan lists them and the tile
+// kernels run them first.
+__host__ __device__ inline int heavy_min_of(long npart, int heavy_cap) {
+  return (int)((npart + heavy_cap - 1) / heavy_cap);
+}
 // Tile depth: the largest of 8, 16, 32, 64 (<= tz_max) dividing nm (64 by default:
 // deeper tiles stage fewer halo cells per particle).
 Bins make_bins(int nm, int tz_max = 64);
@@ -108,6 +117,7 @@ BinBuffers carve_bins(void* base, long npart, const Bins& b);
 
 hipError_t launch_bin_count(Lattice lat, Bins b, const float* s, BinBuffers bb, hipStream_t st);
 // clear_next also zeroes count_next for a binning gather later in the step.
+// Also lists the crowded tiles (bb.heavy) for the tile kernels.
 hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t st);
 hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
 // Tile deposit: each tile accumulates its own particles and the boundary classes of

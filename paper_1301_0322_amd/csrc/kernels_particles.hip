@@ -19,8 +19,7 @@ namespace cola {
 constexpr int kPartThreads = 256;
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ long xcd_block(long nblocks_padded) {
-  const long b = blockIdx.x;
+__device__ __forceinline__ long xcd_block(long nblocks_padded, long b = blockIdx.x) {
   return (b % kXcds) * (nblocks_padded / kXcds) + b / kXcds;
 }
 
@@ -222,8 +221,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_sums(const int* __restric
 }
 
 // One block: exclusive scan of the nb chunk sums in place; total to *tot.
-__global__ __launch_bounds__(kScanThreads) void k_scan_top(int* __restrict__ part, int nb, int* __restrict__ tot) {
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int* __restrict__ part, int nb, int* __restrict__ tot,
+                                                           int* __restrict__ heavy) {
   __shared__ int wsum[kScanThreads / 64];
+  if (threadIdx.x == 0) heavy[0] = 0;   // k_heavy_tiles appends after the offsets are final
   int carry = 0;
   for (int c = 0; c < nb; c += kScanThreads) {
     const int i = c + threadIdx.x;
@@ -257,6 +258,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_chunks(const int* __restr
   }
 }
 
+// Crowded tiles: every tile holding more than heavy_min particles (own classes) is
+// appended to heavy[1..] (count in heavy[0]).  With heavy_min = ceil(npart / cap)
+// fewer than cap tiles can qualify, so the list never overflows.  The order within the
+// list does not matter: each tile's result is independent of when it runs.
+__global__ __launch_bounds__(kPartThreads) void k_heavy_tiles(long nbins, const int* __restrict__ offset, int heavy_min,
+                                                              int* __restrict__ heavy) {
+  const long t = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  if (t >= nbins) return;
+  if (offset[(t + 1) * kClasses] - offset[t * kClasses] > heavy_min) heavy[1 + atomicAdd(heavy, 1)] = (int)t;
+}
+
 __global__ __launch_bounds__(kPartThreads) void k_bin_scatter(long npart, const int2* __restrict__ key_rank,
                                                               const int* __restrict__ offset, int* __restrict__ idx) {
   const long p = (long)blockIdx.x * kPartThreads + threadIdx.x;
@@ -270,36 +282,60 @@ struct TileGeom {
   int lo[3];
 };
 
-// Tile of this block.  Each XCD (blocks b with b % 8 = k) takes the slab of tile
-// planes bx in [k nbx/8, (k+1) nbx/8) and walks it with bz fastest, then bx, then by,
-// so a tile's z, x and y neighbours (whose cells overlap its +1 halo) run within a
-// few dozen blocks of it on the same XCD and share its L2.  Meshes with nbx not a
-// multiple of 8 fall back to the plain slab order.
+// Tile of this block.  The first b.heavy_cap blocks take the crowded tiles listed
+// by k_heavy_tiles (blocks past the list's length exit), so the tiles whose blocks
+// loop over many particle batches start first instead of trailing the grid.  The
+// other blocks (virtual index v = block - heavy_cap, with v % 8 the block's XCD) map
+// v to a tile: each XCD takes the slab of tile planes bx in [k nbx/8, (k+1) nbx/8)
+// and walks it with bz fastest, then bx, then by, so a tile's z, x and y neighbours
+// (whose cells overlap its +1 halo) run within a few dozen blocks of it on the same
+// XCD and share its L2.  Meshes with nbx not a multiple of 8 fall back to the plain
+// slab order.  `listed` tells the caller whether the tile came from the list; a
+// block that was not listed must skip a crowded tile (tile_is_listed), which a
+// listed block handles.
 template <int TZ>
-__device__ __forceinline__ bool tile_geom(const Bins& b, TileGeom& g) {
-  const long nb = (b.nbins + kXcds - 1) / kXcds * kXcds;
+__device__ __forceinline__ bool tile_geom(const Bins& b, const int* heavy, TileGeom& g, bool& listed) {
   int bx, by, bz;
-  if (b.nbx % kXcds == 0) {
-    const long local = (long)blockIdx.x / kXcds;
-    const int sx = b.nbx / kXcds;
-    if (local >= b.nbins / kXcds) return false;
-    bz = (int)(local % b.nbz);
-    const long r = local / b.nbz;
-    bx = (int)(blockIdx.x % kXcds) * sx + (int)(r % sx);
-    by = (int)(r / sx);
-    g.bin = (int)(((long)bx * b.nby + by) * b.nbz + bz);
-  } else {
-    g.bin = (int)xcd_block(nb);
-    if (g.bin >= b.nbins) return false;
+  const long blk = blockIdx.x;
+  listed = blk < b.heavy_cap;
+  if (listed) {
+    if (blk >= heavy[0]) return false;
+    g.bin = heavy[1 + blk];
     bz = g.bin % b.nbz;
     const int r = g.bin / b.nbz;
     bx = r / b.nby;
     by = r % b.nby;
+  } else {
+    const long v = blk - b.heavy_cap;
+    const long nb = (b.nbins + kXcds - 1) / kXcds * kXcds;
+    if (b.nbx % kXcds == 0) {
+      const long local = v / kXcds;
+      const int sx = b.nbx / kXcds;
+      if (local >= b.nbins / kXcds) return false;
+      bz = (int)(local % b.nbz);
+      const long r = local / b.nbz;
+      bx = (int)(v % kXcds) * sx + (int)(r % sx);
+      by = (int)(r / sx);
+      g.bin = (int)(((long)bx * b.nby + by) * b.nbz + bz);
+    } else {
+      g.bin = (int)xcd_block(nb, v);
+      if (g.bin >= b.nbins) return false;
+      bz = g.bin % b.nbz;
+      const int r = g.bin / b.nbz;
+      bx = r / b.nby;
+      by = r % b.nby;
+    }
   }
   g.lo[0] = bx * kTX;
   g.lo[1] = by * kTY;
   g.lo[2] = bz * TZ;
   return true;
+}
+
+// Whether a tile with `own` particles (its own classes) is on the crowded list: the
+// same test as k_heavy_tiles.
+__device__ __forceinline__ bool tile_is_listed(const Lattice& lat, const Bins& b, int own) {
+  return own > heavy_min_of(lat.npart, b.heavy_cap);
 }
 
 // Tile-local stencil of the particle in slot `slot` of s with Lagrangian index `lagi`;
@@ -396,13 +432,15 @@ template <int TZ, class ACC>
 __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
                                                                 const int* __restrict__ lag,
                                                                 const int* __restrict__ idx,
-                                                                const int* __restrict__ offset, float* __restrict__ rho,
+                                                                const int* __restrict__ offset,
+                                                                const int* __restrict__ heavy, float* __restrict__ rho,
                                                                 float mass, const float* __restrict__ weight) {
   using D = TileDims<TZ>;
   __shared__ ACC tile[D::CORE];
   __shared__ int rbeg[kDepRanges], rpre[kDepRanges + 1], rmask[kDepRanges];
   TileGeom g;
-  if (!tile_geom<TZ>(bins, g)) return;
+  bool listed;
+  if (!tile_geom<TZ>(bins, heavy, g, listed)) return;
   for (int i = threadIdx.x; i < D::CORE; i += D::TT) tile[i] = 0;
   if (threadIdx.x < 64) {
     // lane r < 20 describes range r: r = 0 own tile, then the (mask, class) pairs
@@ -457,6 +495,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
     if (lane == 0) rpre[0] = 0;
   }
   __syncthreads();
+  if (!listed && tile_is_listed(lat, bins, rpre[1])) return;   // block-uniform
   const int total = rpre[kDepRanges];
   constexpr int U = 2;   // particles per lane per batch, so their dependent loads overlap
   for (int base = 0; base < total; base += U * D::TT) {   // block-uniform trip count
@@ -524,19 +563,22 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
 // ---------------------------------------------------------------------------------
 template <int TZ, int MODE, bool BIN_NEXT>
 __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_tiles(Lattice lat, Bins bins, const int* __restrict__ idx,
-                                                               const int* __restrict__ offset, GatherArgs g,
+                                                               const int* __restrict__ offset,
+                                                               const int* __restrict__ heavy, GatherArgs g,
                                                                KickArgs k, int2* __restrict__ key_rank_next,
                                                                int* __restrict__ count_next) {
   using D = TileDims<TZ>;
   __shared__ float tile[3 * D::EXT];
   TileGeom t;
-  if (!tile_geom<TZ>(bins, t)) return;
+  bool listed;
+  if (!tile_geom<TZ>(bins, heavy, t, listed)) return;
+  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
+  if (!listed && tile_is_listed(lat, bins, end - beg)) return;
   const float* gf[3] = {g.g0, g.g1, g.g2};
   const TileGeom& T_ = t;
   stage_fields<TZ, 3>(t, lat.nm, gf, tile);
   __syncthreads();
   const long n = lat.npart;
-  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
   for (int base = beg; base < end; base += D::TT) {   // block-uniform trip count
     const int i = base + threadIdx.x;
     const unsigned p = (unsigned)idx[i < end ? i : base];
@@ -607,11 +649,15 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_tiles(Lattice lat, 
 template <int TZ>
 __global__ __launch_bounds__(TileDims<TZ>::TT) void k_grad_gather(Lattice lat, Bins bins, const int* __restrict__ idx,
                                                               const int* __restrict__ offset,
+                                                              const int* __restrict__ heavy,
                                                               const float* __restrict__ s, AdjGatherArgs ga) {
   using D = TileDims<TZ>;
   __shared__ float tile[4 * D::EXT];
   TileGeom t;
-  if (!tile_geom<TZ>(bins, t)) return;
+  bool listed;
+  if (!tile_geom<TZ>(bins, heavy, t, listed)) return;
+  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
+  if (!listed && tile_is_listed(lat, bins, end - beg)) return;
   const bool with_g = ga.g0 != nullptr;
   if (with_g) {
     const float* f[4] = {ga.g0, ga.g1, ga.g2, ga.rbar};
@@ -622,7 +668,6 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_grad_gather(Lattice lat, B
   }
   __syncthreads();
   const long n = lat.npart;
-  const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
   for (int i = beg + threadIdx.x; i < end; i += D::TT) {
     const unsigned p = (unsigned)idx[i];
     float sv[3], fr[3];
@@ -712,15 +757,18 @@ __device__ __forceinline__ void load_record(const SortedState& st, long n, int j
 template <int TZ, int MODE>
 __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat, Bins bins, SortedState src,
                                                                 SortedState dst, const int* __restrict__ idx,
-                                                                const int* __restrict__ offset, GatherArgs g,
+                                                                const int* __restrict__ offset,
+                                                                const int* __restrict__ heavy, GatherArgs g,
                                                                 KickArgs k, int2* __restrict__ key_rank_next,
                                                                 int* __restrict__ count_next) {
   using D = TileDims<TZ>;
   __shared__ float tile[3 * D::EXT];
   TileGeom t;
-  if (!tile_geom<TZ>(bins, t)) return;
+  bool listed;
+  if (!tile_geom<TZ>(bins, heavy, t, listed)) return;
   const long n = lat.npart;
   const int beg = offset[(long)t.bin * kClasses], end = offset[(long)(t.bin + 1) * kClasses];
+  if (!listed && tile_is_listed(lat, bins, end - beg)) return;
   // The first batch of particle reads is issued before the force tile is staged,
   // so both are in flight together (most tiles hold one batch or less); in crowded
   // tiles each batch's reads are issued before the previous batch is processed.
@@ -863,15 +911,18 @@ Bins make_bins(int nm, int tz_max) {
   b.nbz = nm / b.tz;
   b.nbins = (long)b.nbx * b.nby * b.nbz;
   b.nkeys = b.nbins * kClasses;
+  b.heavy_cap = (int)((b.nbins + 16 * kXcds - 1) / (16 * kXcds) * kXcds);   // ~nbins / 16, a multiple of 8
   return b;
 }
 
 static size_t count_len(const Bins& b) { return (size_t)((b.nkeys + 4) / 4 * 4); }
 static size_t scan_chunks(const Bins& b) { return (size_t)((b.nkeys + kScanChunk - 1) / kScanChunk); }
 
+static size_t part_len(const Bins& b) { return (scan_chunks(b) + 4) / 4 * 4; }
+
 size_t bin_workspace_bytes(long npart, const Bins& b) {
-  return npart * sizeof(int2) + npart * sizeof(int) + 3 * count_len(b) * sizeof(int) +
-         (scan_chunks(b) + 4) / 4 * 4 * sizeof(int);
+  return npart * sizeof(int2) + npart * sizeof(int) + 3 * count_len(b) * sizeof(int) + part_len(b) * sizeof(int) +
+         (size_t)(b.heavy_cap + 4) / 4 * 4 * sizeof(int);
 }
 
 BinBuffers carve_bins(void* base, long npart, const Bins& b) {
@@ -889,7 +940,10 @@ BinBuffers carve_bins(void* base, long npart, const Bins& b) {
   bb.offset = reinterpret_cast<int*>(c);
   c += cnt * sizeof(int);
   bb.part = reinterpret_cast<int*>(c);
+  c += part_len(b) * sizeof(int);
+  bb.heavy = reinterpret_cast<int*>(c);
   bb.count_len = (long)cnt;
+  bb.npart = npart;
   return bb;
 }
 
@@ -902,7 +956,10 @@ hipError_t launch_fill(float* p, long n, float value, hipStream_t st) {
 }
 
 static unsigned part_blocks(long npart) { return (unsigned)((npart + kPartThreads - 1) / kPartThreads); }
-static unsigned tile_blocks(const Bins& b) { return (unsigned)((b.nbins + kXcds - 1) / kXcds * kXcds); }
+// Listed crowded tiles first, then every tile in XCD order (tile_geom).
+static unsigned tile_blocks(const Bins& b) {
+  return (unsigned)(b.heavy_cap + (b.nbins + kXcds - 1) / kXcds * kXcds);
+}
 
 #define COLA_TZ_DISPATCH(tz, CALL) \
   switch (tz) {                    \
@@ -926,8 +983,10 @@ hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t s
   const unsigned nb = (unsigned)scan_chunks(b);
   hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(kScanThreads), 0, st, bb.count, n, bb.part,
                      clear_next ? bb.count_next : nullptr, (int)bb.count_len);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, bb.part, (int)nb, bb.offset + n);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, bb.part, (int)nb, bb.offset + n, bb.heavy);
   hipLaunchKernelGGL(k_scan_chunks, dim3(nb), dim3(kScanThreads), 0, st, bb.count, n, bb.part, bb.offset);
+  hipLaunchKernelGGL(k_heavy_tiles, dim3((unsigned)((b.nbins + kPartThreads - 1) / kPartThreads)), dim3(kPartThreads), 0,
+                     st, b.nbins, bb.offset, heavy_min_of(bb.npart, b.heavy_cap), bb.heavy);
   return hipGetLastError();
 }
 
@@ -941,10 +1000,10 @@ hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, fl
                           hipStream_t st, const float* weight, const int* lag) {
   if (weight)
     COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float>), dim3(tile_blocks(b)), dim3(TileDims<TZ>::TT),
-                                              0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass, weight))
+                                              0, st, lat, b, s, lag, bb.idx, bb.offset, bb.heavy, rho, mass, weight))
   else
     COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long>), dim3(tile_blocks(b)),
-                                              dim3(TileDims<TZ>::TT), 0, st, lat, b, s, lag, bb.idx, bb.offset, rho, mass,
+                                              dim3(TileDims<TZ>::TT), 0, st, lat, b, s, lag, bb.idx, bb.offset, bb.heavy, rho, mass,
                                               weight))
   return hipGetLastError();
 }
@@ -954,16 +1013,16 @@ static void gather_tz(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_nex
                       hipStream_t st) {
   const dim3 grid(tile_blocks(b)), block(TileDims<TZ>::TT);
   if (mode == kGatherForce)
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherForce, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a, k,
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherForce, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy, a, k,
                        bb.key_rank, bb.count_next);
   else if (mode == kGatherKickDrift && bin_next)
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, true>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a,
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, true>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy, a,
                        k, bb.key_rank, bb.count_next);
   else if (mode == kGatherKickDrift)
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset,
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy,
                        a, k, bb.key_rank, bb.count_next);
   else
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherFinish, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, a,
+    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherFinish, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy, a,
                        k, bb.key_rank, bb.count_next);
 }
 
@@ -980,9 +1039,9 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
   const dim3 grid(tile_blocks(b)), block(TileDims<TZ>::TT);
   if (mode == kGatherKickDrift)
     hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, src, dst, bb.idx,
-                       bb.offset, a, k, bb.key_rank, bb.count_next);
+                       bb.offset, bb.heavy, a, k, bb.key_rank, bb.count_next);
   else
-    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherFinish>), grid, block, 0, st, lat, b, src, dst, bb.idx, bb.offset,
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherFinish>), grid, block, 0, st, lat, b, src, dst, bb.idx, bb.offset, bb.heavy,
                        a, k, bb.key_rank, bb.count_next);
 }
 
@@ -1037,7 +1096,7 @@ hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t s
 
 hipError_t launch_grad_gather(Lattice lat, Bins b, BinBuffers bb, const float* s, AdjGatherArgs ga, hipStream_t st) {
   COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_grad_gather<TZ>, dim3(tile_blocks(b)), dim3(TileDims<TZ>::TT), 0, st, lat, b,
-                                            bb.idx, bb.offset, s, ga));
+                                            bb.idx, bb.offset, bb.heavy, s, ga));
   return hipGetLastError();
 }
 
