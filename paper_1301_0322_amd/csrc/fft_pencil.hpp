@@ -117,7 +117,7 @@ __device__ __forceinline__ void dft_reg(float2* x) {
 constexpr int pencil_r2(int L) {
   return L == 8 ? 4 : L == 12 ? 4 : L == 16 ? 4 : L == 24 ? 8 : L == 32 ? 8 : L == 48 ? 8 : L == 64 ? 8
        : L == 96 ? 16 : L == 128 ? 16 : L == 192 ? 16 : L == 256 ? 16 : L == 384 ? 16 : L == 512 ? 32
-       : L == 768 ? 32 : L == 1024 ? 32 : 0;
+       : L == 768 ? 24 : L == 1024 ? 32 : 0;
 }
 constexpr int pmax(int a, int b) { return a > b ? a : b; }
 constexpr int round_up(int a, int m) { return (a + m - 1) / m * m; }

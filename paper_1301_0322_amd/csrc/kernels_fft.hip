@@ -40,14 +40,19 @@ constexpr int floor_pow2(int v) { return v < 2 ? 1 : 2 * floor_pow2(v / 2); }
 template <int N>
 using ZHPencil = Pencil<N / 2, floor_pow2(min_i(z_rows<N / 2>(), pmax(1, 128 / (N / 2 / pencil_r2(N / 2))))), true>;
 
-// A column width is usable when it divides n/2, the LDS exchange stays within 64 KB and
-// the block within 1024 threads.
+// A column width is usable when it divides n/2, the LDS exchange fits in kColLdsMax
+// and the block stays within 1024 threads.
+constexpr size_t kColLdsMax = 104 * 1024;
 template <int N, int B>
 constexpr bool col_ok() {
-  return B >= 2 && B <= pow2_factor(N / 2) && N * B <= 8192 && B * (N / pencil_r2(N)) <= 1024;
+  return B >= 2 && B <= pow2_factor(N / 2) && B * (N / pencil_r2(N)) <= 1024 &&
+         Pencil<N, B, false>::LDS * sizeof(float2) <= kColLdsMax;
 }
-constexpr int col_width_default(int n) {
-  return (n * 16 <= 8192 && pow2_factor(n / 2) >= 16) ? 16 : (pow2_factor(n / 2) >= 8 && n * 8 <= 8192) ? 8 : 4;
+// The widest of 16, 8, 4 columns that is usable: 16 columns are 128-byte runs per row,
+// the width at which the strided passes reach full HBM bandwidth.
+template <int N>
+constexpr int col_width_default() {
+  return col_ok<N, 16>() ? 16 : col_ok<N, 8>() ? 8 : 4;
 }
 
 __device__ __forceinline__ int pick_comp(int c, int nx, int ny, int nz) {
@@ -447,7 +452,7 @@ static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_out
 template <int N>
 static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
                         long inner_stride, int ncols, const float2* tw, int width, int reverse, hipStream_t st) {
-  switch (width ? width : col_width_default(N)) {
+  switch (width ? width : col_width_default<N>()) {
     case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
     case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
     case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
@@ -474,7 +479,7 @@ static hipError_t xmul_tb(int mode, const float2* in, FieldPtrs out, int nout, M
 
 // Default x-pass width: the widest valid tile (128-byte row segments at 16 columns).
 template <int N>
-constexpr int xmul_width() { return col_width_default(N); }
+constexpr int xmul_width() { return col_width_default<N>(); }
 
 template <int N>
 static hipError_t xmul_t(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,

@@ -157,6 +157,45 @@ def test_variant_run_matches_oracle(flags):
     assert rel <= 1e-4, rel
 
 
+@pytest.mark.parametrize("np_side,nm", [(32, 96), (16, 48)])
+def test_paper_mesh_ratio_run_matches_oracle(np_side, nm):
+    # the paper's 3x mesh refinement (3^3 cells per particle), same bars as the 2x runs
+    cfg = cola.Config(np=np_side, nm=nm)
+    oc = _ocfg(cfg)
+    w = inputs.white_noise(np_side, 1301)
+    announce(f"run {np_side}/{nm}")
+    x, v, p = cola.run(cfg, dev(w))
+    x, v = host(x), host(v)
+    rx, rv, rs = ocola.run(w.astype(np.float64), oc)
+    rx = rx.reshape(3, -1).numpy()
+    err = periodic_max_err(x, rx, cfg.box)
+    assert err <= 1e-3 * cfg.box, err
+    assert rel_l2(v, rv.reshape(3, -1).numpy()) < 1e-4
+    pk_gpu, _ = power.power_of_positions(torch.from_numpy(x.astype(np.float64)), cfg.nm, cfg.box)
+    pk_orc, _ = power.power_of_positions(torch.from_numpy(rx), cfg.nm, cfg.box)
+    rel = (pk_gpu / pk_orc - 1.0).abs().max().item()
+    assert rel <= 1e-4, rel
+
+
+def test_paper_mesh_full_size_run_properties():
+    """256^3 particles on the paper's 768^3 mesh: momentum and range invariants."""
+    cfg = cola.Config(np=256, nm=768)
+    announce("run 256/768")
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        w = torch.empty(256**3, dtype=torch.float32, device="cuda")
+        plan.noise(1302, w)
+        p = cola.Particles.empty(256)
+        x = torch.empty((3, 256**3), dtype=torch.float32, device="cuda")
+        v = torch.empty_like(x)
+        plan.run(w, p, x, v, ws)
+        xs, vres = host(x), host(p.v)
+        del ws, w, p, x, v
+        torch.cuda.empty_cache()
+    assert np.isfinite(xs).all() and xs.min() >= 0.0 and xs.max() < cfg.box
+    assert np.abs(vres.astype(np.float64).sum(axis=1)).max() < 1e-4 * np.abs(vres).sum() / 3
+
+
 @pytest.mark.parametrize("flags", [0, _PM | _LOG])
 def test_step_by_step_equals_run(flags):
     cfg = cola.Config(np=16, nm=32, flags=flags)
