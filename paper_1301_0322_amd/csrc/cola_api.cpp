@@ -170,6 +170,7 @@ Lattice lattice(cola_plan p) {
   l.ratio = p->cfg.nm / p->cfg.np;
   l.inv_dx = (float)(p->cfg.nm / p->cfg.box);
   l.npart = cube(p->cfg.np);
+  set_lattice_divisor(l);
   return l;
 }
 

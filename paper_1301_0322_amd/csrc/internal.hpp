@@ -78,7 +78,18 @@ struct Lattice {
   int ratio;        // nm / np
   float inv_dx;     // nm / L
   long npart;       // np^3
+  // x / np for x < 2^31 as (x * np_magic) >> (31 + np_shift): np_shift = ceil(log2 np),
+  // np_magic = floor(2^(31 + np_shift) / np) + 1 (Granlund and Montgomery 1994, the
+  // round-up method; exact because np_magic * np lies in (2^(31+l), 2^(31+l) + np]).
+  unsigned np_magic;
+  int np_shift;
 };
+inline void set_lattice_divisor(Lattice& l) {
+  int s = 0;
+  while ((1L << s) < l.np) ++s;
+  l.np_shift = s;
+  l.np_magic = (unsigned)((1ULL << (31 + s)) / (unsigned long long)l.np + 1);
+}
 
 hipError_t launch_fill(float* p, long n, float value, hipStream_t st);
 

@@ -74,8 +74,12 @@ struct TileDims {
 // enough for any supported size: a cell holds at most the total mass nm^3 <= 2^30.
 constexpr float kFixScale = 4294967296.f;   // 2^32
 __device__ __forceinline__ void tile_add(float* p, float x) { atomicAdd(p, x); }
+// x >= 0 (a mass share): round(x 2^32) from the exact split x = h + r, h = floor(x),
+// as h 2^32 + rint(r 2^32); r 2^32 < 2^32 - 2^8 for a float r < 1.
 __device__ __forceinline__ void tile_add(unsigned long long* p, float x) {
-  atomicAdd(p, (unsigned long long)__float2ll_rn(x * kFixScale));
+  const float h = floorf(x);
+  const unsigned lo = (unsigned)rintf((x - h) * kFixScale);
+  atomicAdd(p, ((unsigned long long)(unsigned)h << 32) | lo);
 }
 __device__ __forceinline__ float tile_value(float v) { return v; }
 __device__ __forceinline__ float tile_value(unsigned long long v) { return (float)(long long)v * (1.f / kFixScale); }
@@ -89,12 +93,16 @@ __device__ __forceinline__ int base_cell(int lag, int ratio, float s, float inv_
   return ((unsigned)c < (unsigned)nm) ? c : wrap(c, nm);
 }
 
+__device__ __forceinline__ unsigned div_np(const Lattice& lat, unsigned x) {
+  return (unsigned)(((unsigned long long)x * lat.np_magic) >> (31 + lat.np_shift));
+}
 __device__ __forceinline__ void lag_index(const Lattice& lat, unsigned p, int li[3]) {
   const unsigned n = (unsigned)lat.np;
-  const unsigned q = p / n;
+  const unsigned q = div_np(lat, p);
+  const unsigned r = div_np(lat, q);
   li[2] = (int)(p - q * n);
-  li[1] = (int)(q % n);
-  li[0] = (int)(q / n);
+  li[1] = (int)(q - r * n);
+  li[0] = (int)r;
 }
 
 struct Stencil {
@@ -113,8 +121,10 @@ __device__ __forceinline__ Stencil stencil_of(const Lattice& lat, unsigned p, co
 
 template <int TZ>
 __device__ __forceinline__ int key_of(const Bins& b, const int c[3]) {
-  const int tile = ((c[0] / kTX) * b.nby + c[1] / kTY) * b.nbz + c[2] / TZ;
-  const int cls = ((c[0] % kTX) == kTX - 1) | (((c[1] % kTY) == kTY - 1) << 1) | (((c[2] % TZ) == TZ - 1) << 2);
+  // base cells are wrapped (non-negative): unsigned shifts and masks
+  const unsigned x = (unsigned)c[0], y = (unsigned)c[1], z = (unsigned)c[2];
+  const int tile = (int)(((x / kTX) * b.nby + y / kTY) * b.nbz + z / TZ);
+  const int cls = ((x % kTX) == kTX - 1) | (((y % kTY) == kTY - 1) << 1) | (((z % TZ) == TZ - 1) << 2);
   return tile * kClasses + cls;
 }
 
@@ -509,8 +519,10 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
       in[u] = i < total;
       const int ii = in[u] ? i : 0;
       int r = 0;
+      if (ii >= rpre[1]) {   // past the tile's own particles: find the neighbour range
 #pragma unroll
-      for (int q = 1; q < kDepRanges; ++q) r += (rpre[q] <= ii) ? 1 : 0;
+        for (int q = 1; q < kDepRanges; ++q) r += (rpre[q] <= ii) ? 1 : 0;
+      }
       msk[u] = rmask[r];
       const unsigned slot = in[u] ? (unsigned)idx[rbeg[r] + ii - rpre[r]] : 0u;
       if (lag) {   // packed state: positions in the first float4 of the slot
@@ -529,9 +541,10 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
     for (int u = 0; u < U; ++u) {
       if (!in[u]) continue;
       const Stencil st = stencil_of(lat, lg[u], sv[u]);
-      const int rx = (st.c[0] % kTX) - ((msk[u] & 1) ? kTX : 0);
-      const int ry = (st.c[1] % kTY) - ((msk[u] & 2) ? kTY : 0);
-      const int rz = (st.c[2] % TZ) - ((msk[u] & 4) ? TZ : 0);
+      // base cells are wrapped (non-negative), so the tile-local parts are masks
+      const int rx = (int)((unsigned)st.c[0] % kTX) - ((msk[u] & 1) ? kTX : 0);
+      const int ry = (int)((unsigned)st.c[1] % kTY) - ((msk[u] & 2) ? kTY : 0);
+      const int rz = (int)((unsigned)st.c[2] % TZ) - ((msk[u] & 4) ? TZ : 0);
       const float mw = weight ? mass * weight[lg[u]] : mass;
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
