@@ -51,9 +51,10 @@ def stage_bytes(np_side: int, nm: int) -> dict:
         "deposit": 12 * P + 4 * R,
         "fft_z_fwd": 4 * R + 8 * C,
         "fft_y_fwd": 16 * C,
-        "fft_x_poisson": 8 * C + 24 * C,
-        "fft_y_inv": 16 * C,            # one force field per launch
-        "fft_z_inv": 8 * C + 4 * R,     # one force field per launch
+        "fft_x_poisson": 8 * C + 16 * C,   # writes i n_x Phi and Phi
+        "fft_y_inv": 16 * C,               # the x component
+        "fft_y_inv_pair": 8 * C + 16 * C,  # Phi -> i n_y Phi and Phi
+        "fft_z_inv": 8 * C + 4 * R,        # one force component per launch
         "gather_kick_drift": 12 * R + 72 * P,
         "gather_finish": 12 * R + 48 * P + 36 * P,
         "fill": 0,
@@ -68,6 +69,17 @@ def stage_bytes(np_side: int, nm: int) -> dict:
 
 
 def b_alg_step(np_side: int, nm: int) -> int:
+    """Bytes one PM step must move with this pass structure: deposit, z and y forward,
+    the x pass (2 outputs), the y passes (x component; Phi -> y, z components), three z
+    inverse passes, gather + kick + drift: 84 P + 32 R + 112 C."""
+    R = nm**3
+    C = nm * nm * (nm // 2 + 1)
+    return 84 * np_side**3 + 32 * R + 112 * C
+
+
+def b_alg_three_chains(np_side: int, nm: int) -> int:
+    """The same with three independent inverse chains (one per force component):
+    84 P + 32 R + 128 C."""
     R = nm**3
     C = nm * nm * (nm // 2 + 1)
     return 84 * np_side**3 + 32 * R + 128 * C
@@ -373,6 +385,9 @@ def main() -> int:
                      "algorithmic_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms_launch},
         "pm_step": {"ms": pm_step_ms, "particle_steps_per_s": np_side**3 / (pm_step_ms * 1e-3),
                     "b_alg_bytes": b_alg, "hbm_frac": b_alg / (pm_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                    "b_alg_three_chains_bytes": b_alg_three_chains(np_side, nm),
+                    "hbm_frac_three_chains": b_alg_three_chains(np_side, nm) / (pm_step_ms * 1e-3)
+                    / (HBM_PEAK_GBS * 1e9),
                     "timed": f"each COLA step inside cola_run, HIP events around the step only, "
                              f"mean of {steps_rec[1]} steps",
                     "cola_step_call_ms": api_step_ms},

@@ -99,7 +99,7 @@ int cola_plan_create(const cola_config *cfg, cola_plan *out);
 /* Frees the plan and the device tables it uploaded.  NULL is accepted. */
 int cola_plan_destroy(cola_plan plan);
 
-/* Bytes of workspace every call below needs: three nm^3 float meshes, the
+/* Bytes of workspace every call below needs: four nm^3 float meshes, the
  * per-step particle binning buffers (12 bytes per particle, three int arrays of
  * one entry per 8x8xtz tile, the halo faces of every tile) and two tile-sorted
  * copies of the particle state used by cola_run (104 bytes per particle). */

@@ -53,13 +53,13 @@ enum Stage : int {
   kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStZFwd, kStYFwd, kStXPoisson,
   kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
   kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kStAdjKick, kStAdjDeposit, kStAdjFft, kStAdjGather,
-  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kNumStages
+  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kStYInvPair, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
   "bin_count", "bin_scan", "bin_scatter", "deposit", "fft_z_fwd", "fft_y_fwd",
   "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
   "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
-  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort"};
+  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort", "fft_y_inv_pair"};
 
 // Trace levels: 1 records an event pair around every kernel launch, 2 only around
 // each whole COLA step of cola_run (stage run_step), so step times carry no
@@ -185,8 +185,9 @@ int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const flo
       p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, w, st, reverse); }));
 }
 
-// Workspace: three real nm^3 meshes, then the binning buffers.
-size_t mesh_floats(cola_plan p) { return 3 * (size_t)cube(p->cfg.nm); }
+// Workspace: four real nm^3 meshes (the three force components and the scalar field
+// of the force passes), then the binning buffers.
+size_t mesh_floats(cola_plan p) { return 4 * (size_t)cube(p->cfg.nm); }
 
 // parity selects which of the two tile-count arrays holds the current counts
 // (cola_run alternates them: a step's gather counts into the other one).
@@ -254,19 +255,35 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   const double kf = 2.0 * M_PI / p->cfg.box;
   MulArgs m{};
   m.c = (float)(1.5 * p->cfg.omega_m * a / (kf * (double)r));
+  // The gradient i k_j phi_k needs its factor k_j while axis j is still in k-space:
+  // the x pass writes i n_x Phi (into g0) and Phi (into g3), Phi = c X / n^2 after the
+  // inverse x transform; the y pass of Phi writes i n_y Phi (g1) and Phi (g2); the z
+  // pass applies i n_z to g2.  Two x outputs and one y input fewer than three separate
+  // gradient chains, the same operators.
+  float* g3 = ws + 3 * r;
   COLA_HIP(traced(p, kStXPoisson, st, [&] {
-    return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(g0), fields({g0, g1, g2}), 3, m, tw,
+    return launch_xmul(n, kMulGradPair, reinterpret_cast<float2*>(g0), fields({g0, g3}), 2, m, tw,
                        p->fft_width[1], st);
   }));
   EpiArgs e{};
   e.scale = 1.0f;
   e.reverse = 1;
-  for (float* g : {g2, g1, g0}) {
-    COLA_TRY(ypass(p, kStYInv, n, 1, fields({g}), 1, tw, st));
+  const int h = n / 2;
+  COLA_HIP(traced(p, kStYInvPair, st, [&] {
+    return launch_col_pair(n, reinterpret_cast<const float2*>(g3), reinterpret_cast<float2*>(g2),
+                           reinterpret_cast<float2*>(g1), n, (long)n * h, h, h, tw, width_for(p, n, 0), st);
+  }));
+  for (float* g : {g1, g2}) {
+    e.deriv = g == g2;
     COLA_HIP(traced(p, kStZInv, st, [&] {
       return launch_zinv(n, fields({g}), fields({g}), 1, (long)n * n, tw, kEpiStore, e, st);
     }));
   }
+  e.deriv = 0;
+  COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0}), 1, tw, st));
+  COLA_HIP(traced(p, kStZInv, st, [&] {
+    return launch_zinv(n, fields({g0}), fields({g0}), 1, (long)n * n, tw, kEpiStore, e, st);
+  }));
   return COLA_OK;
 }
 

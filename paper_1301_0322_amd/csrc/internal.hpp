@@ -15,8 +15,10 @@ struct FieldPtrs {
 
 // k-space multiplier applied between the forward and inverse x transforms.
 enum MulMode : int {
-  kMulGrad = 0,   // out_j = c * i n_j / n^2 * X            (3 outputs)
-  kMulLpt1 = 1,   // s1_j = i n_j tab[n^2] X, phi_ij = kf n_i n_j tab[n^2] X  (9 outputs)
+  kMulGrad = 0,      // out_j = c * i n_j / n^2 * X            (3 outputs)
+  kMulLpt1 = 1,      // s1_j = i n_j tab[n^2] X, phi_ij = kf n_i n_j tab[n^2] X  (9 outputs)
+  kMulGradPair = 2,  // out_0 = c * i n_x / n^2 * X, out_1 = c / n^2 * X  (2 outputs): the y and z
+                     // components follow from out_1 in the y and z passes (i n_y, i n_z there)
 };
 
 struct MulArgs {
@@ -40,6 +42,7 @@ struct EpiArgs {
   float* v;
   long comp_stride;
   int reverse;        // rows from the last block to the first (memory-side cache reuse)
+  int deriv;          // multiply mode k by i k before the transform (z derivative)
 };
 
 bool fft_size_supported(int n);
@@ -63,9 +66,15 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, int n_outer,
                       long outer_stride, long inner_stride, int ncols, const float2* tw, int width,
                       hipStream_t st, int reverse = 0);
+// Inverse column pass of one field with two outputs: out_d = inverse transform of
+// i n X (n the signed mode number along the column) and out_p = inverse transform of
+// X.  The three buffers are distinct.
+hipError_t launch_col_pair(int n, const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
+                           long inner_stride, int ncols, const float2* tw, int width, hipStream_t st,
+                           int reverse = 0);
 // x pass with the k-space multiplier: forward x transform of `in`, multiply, inverse
 // x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row.
-// kMulGrad requires nout = 3, kMulLpt1 1..9.
+// kMulGrad requires nout = 3, kMulGradPair 2, kMulLpt1 1..9.
 hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m,
                        const float2* tw, int width, hipStream_t st);
 // Whether `width` columns per tile is a valid strided-pass shape for length n.

@@ -19,6 +19,7 @@
 namespace cola {
 
 constexpr int pow2_factor(int v) { return (v & (-v)); }
+constexpr int kXcdsFft = 8;   // XCDs; blocks b and b + 8 run on the same one
 constexpr int min_i(int a, int b) { return a < b ? a : b; }
 
 // Rows per block of the z passes: a power of two with at most 256 threads and an LDS
@@ -143,6 +144,16 @@ __global__ __launch_bounds__(ZPencil<N>::T) void k_zinv(FieldPtrs in, FieldPtrs 
   float2 q[P::UB][P::R1];
   P::load_b(q, in.p[f] + row0 * M, M);
   load_twiddles(stw, tw, N);
+  if (e.deriv) {
+    // z derivative: mode k (0 <= k < n/2) times i k, before the Hermitian pairing
+#pragma unroll
+    for (int u = 0; u < P::UB; ++u) {
+      int b, j2;
+      P::b_unit(u, b, j2);
+#pragma unroll
+      for (int j1 = 0; j1 < P::R1; ++j1) q[u][j1] = mul_si<1>(c_scale(q[u][j1], (float)(j2 + P::R2 * j1)));
+    }
+  }
   __syncthreads();
   float2 a[P::R2];
   zinv_regs<P, N>(q, a, ex, stw);
@@ -234,6 +245,52 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, 
   P::store_b(q, out.p[f] + origin, inner_stride);
 }
 
+// Inverse column pass with two outputs from one tile of columns: out_d gets the
+// inverse transform of i n X (n = m for m <= n/2, else m - n, m the position along
+// the column) and out_p that of X; neither may alias in.  Each tile is read by two
+// blocks, one per output, 8 block indices apart (the same XCD, dispatched together),
+// so the second read is served by that XCD's L2.
+template <int N, int B>
+__global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const float2* __restrict__ in,
+                                                                     float2* __restrict__ out_p,
+                                                                     float2* __restrict__ out_d, long outer_stride,
+                                                                     long inner_stride, int ntiles_c, long ntiles,
+                                                                     const float2* __restrict__ tw, int reverse) {
+  using P = Pencil<N, B, false>;
+  __shared__ __align__(16) float2 ex[P::LDS];
+  __shared__ float2 stw[N];
+  long tile;
+  int deriv;
+  if (ntiles % kXcdsFft == 0) {
+    const long g = blockIdx.x / (2 * kXcdsFft), w = blockIdx.x % (2 * kXcdsFft);
+    tile = g * kXcdsFft + w % kXcdsFft;
+    deriv = w < kXcdsFft;
+  } else {
+    tile = blockIdx.x / 2;
+    deriv = (blockIdx.x % 2) == 0;
+  }
+  if (reverse) tile = ntiles - 1 - tile;
+  const int tc = (int)(tile % ntiles_c);
+  const long o = tile / ntiles_c;
+  const long origin = o * outer_stride + (long)tc * B;
+  float2 a[P::R2];
+  P::load_a(a, in + origin, inner_stride);
+  load_twiddles(stw, tw, N);
+  if (deriv) {
+    int b, i1;
+    P::a_unit(b, i1);
+#pragma unroll
+    for (int i2 = 0; i2 < P::R2; ++i2) {
+      const int m = i1 + P::R1 * i2;
+      a[i2] = mul_si<1>(c_scale(a[i2], (float)(m <= N / 2 ? m : m - N)));
+    }
+  }
+  __syncthreads();
+  float2 q[P::UB][P::R1];
+  P::template fwd_like<1, 1>(a, q, ex, stw);
+  P::store_b(q, (deriv ? out_d : out_p) + origin, inner_stride);
+}
+
 // ---------------------------------------------------------------------------------
 // x pass with multiplier.  Tile = n elements along x (stride n * n/2) x B kz columns
 // at fixed y.  Mode numbers: nx from the row m, ny from y, nz = kz (< n/2).
@@ -274,7 +331,7 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul(const float2*
       const int nsq = nx * nx + ny * ny + nz * nz;
       const bool keep = ny_ok && (m != H) && nsq != 0;
       float w;
-      if constexpr (MODE == kMulGrad) w = ma.c / (float)max(nsq, 1);
+      if constexpr (MODE != kMulLpt1) w = ma.c / (float)max(nsq, 1);
       else w = ma.tab[nsq];
       xs[u][j1] = keep ? c_scale(xs[u][j1], w) : make_float2(0.f, 0.f);
     }
@@ -300,6 +357,11 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul(const float2*
     emit(0, [&](float2 v, int, int m) { return mul_si<1>(c_scale(v, (float)nx_of(m))); });
     emit(1, [&](float2 v, int, int) { return mul_si<1>(c_scale(v, (float)ny)); });
     emit(2, [&](float2 v, int b, int) { return mul_si<1>(c_scale(v, (float)(tc * B + b))); });
+  } else if constexpr (MODE == kMulGradPair) {
+    // i n_x X' and X' itself: the y and z components are i n_y X' and i n_z X', whose
+    // factors are constant along x, so they are applied in the y and z passes instead
+    emit(0, [&](float2 v, int, int m) { return mul_si<1>(c_scale(v, (float)nx_of(m))); });
+    emit(1, [&](float2 v, int, int) { return v; });
   } else {
     for (int o = 0; o < nout; ++o) {
       emit(o, [&](float2 v, int b, int m) {
@@ -461,14 +523,46 @@ static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_oute
 }
 
 template <int N, int B>
+static hipError_t col_pair_tb(const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
+                              long inner_stride, int ncols, const float2* tw, int reverse, hipStream_t st) {
+  if constexpr (col_ok<N, B>()) {
+    if (ncols % B) return hipErrorInvalidValue;
+    constexpr int T = Pencil<N, B, false>::T;
+    const int ntc = ncols / B;
+    const long ntiles = (long)n_outer * ntc;
+    hipLaunchKernelGGL((k_col_pair<N, B>), dim3((unsigned)(2 * ntiles)), dim3(T), 0, st, in, out_p, out_d,
+                       outer_stride, inner_stride, ntc, ntiles, tw, reverse);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+static hipError_t col_pair_t(const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
+                             long inner_stride, int ncols, const float2* tw, int width, int reverse, hipStream_t st) {
+  switch (width ? width : col_width_default<N>()) {
+    case 4: return col_pair_tb<N, 4>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    case 8: return col_pair_tb<N, 8>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    case 16: return col_pair_tb<N, 16>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int B>
 static hipError_t xmul_tb(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
                           hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
     constexpr int T = Pencil<N, B, false>::T;
-    if (mode == kMulGrad ? nout != 3 : (nout < 1 || nout > kMaxFields)) return hipErrorInvalidValue;
+    if (mode == kMulGrad ? nout != 3
+        : mode == kMulGradPair ? nout != 2
+        : (mode != kMulLpt1 || nout < 1 || nout > kMaxFields))
+      return hipErrorInvalidValue;
     dim3 grid(N * ((N / 2) / B));
     if (mode == kMulGrad)
       hipLaunchKernelGGL((k_xmul<N, B, kMulGrad>), grid, dim3(T), 0, st, in, out, nout, m, tw);
+    else if (mode == kMulGradPair)
+      hipLaunchKernelGGL((k_xmul<N, B, kMulGradPair>), grid, dim3(T), 0, st, in, out, nout, m, tw);
     else
       hipLaunchKernelGGL((k_xmul<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, out, nout, m, tw);
     return hipGetLastError();
@@ -497,6 +591,7 @@ static hipError_t xmul_adj_t(int mode, FieldPtrs in, int nin, float2* out, MulAr
                              hipStream_t st) {
   constexpr int B = xmul_width<N>();
   constexpr int T = Pencil<N, B, false>::T;
+  if (mode != kMulGrad && mode != kMulLpt1) return hipErrorInvalidValue;
   if (mode == kMulGrad ? nin != 3 : (nin < 1 || nin > kMaxFields)) return hipErrorInvalidValue;
   dim3 grid(N * ((N / 2) / B));
   if (mode == kMulGrad)
@@ -573,6 +668,20 @@ hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n
 #define COLA_CASE(N) \
   case N:            \
     return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, st);
+    COLA_FOR_EACH_SIZE(COLA_CASE)
+#undef COLA_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_col_pair(int n, const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
+                           long inner_stride, int ncols, const float2* tw, int width, hipStream_t st, int reverse) {
+  if (out_d == in || out_p == in || out_d == out_p) return hipErrorInvalidValue;
+  switch (n) {
+#define COLA_CASE(N) \
+  case N:            \
+    return col_pair_t<N>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:

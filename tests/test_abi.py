@@ -44,12 +44,12 @@ def test_plan_validation():
 
 
 def test_workspace_size():
-    # three nm^3 float meshes, the per-step binning buffers (8 + 4 bytes per
+    # four nm^3 float meshes, the per-step binning buffers (8 + 4 bytes per
     # particle, tile-count arrays, halo faces of every tile) and two tile-sorted
     # copies of the particle state (2 x 13 words per particle)
     for np_side, nm in ((32, 64), (64, 64), (256, 512)):
         with cola.Plan(cola.Config(np=np_side, nm=nm)) as p:
-            meshes = 3 * nm**3 * 4
+            meshes = 4 * nm**3 * 4
             extra = p.workspace_bytes() - meshes - 104 * np_side**3
             assert 12 * np_side**3 < extra < 12 * np_side**3 + 0.4 * nm**3 * 4
 
