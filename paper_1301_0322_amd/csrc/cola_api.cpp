@@ -269,17 +269,19 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   e.scale = 1.0f;
   e.reverse = 1;
   const int h = n / 2;
+  // the y pass reads the tail the x pass wrote last first; the z pass then takes
+  // both of its outputs together from their heads
   COLA_HIP(traced(p, kStYInvPair, st, [&] {
     return launch_col_pair(n, reinterpret_cast<const float2*>(g3), reinterpret_cast<float2*>(g2),
-                           reinterpret_cast<float2*>(g1), n, (long)n * h, h, h, tw, width_for(p, n, 0), st);
+                           reinterpret_cast<float2*>(g1), n, (long)n * h, h, h, tw, width_for(p, n, 0), st, 1);
   }));
-  for (float* g : {g1, g2}) {
-    e.deriv = g == g2;
-    COLA_HIP(traced(p, kStZInv, st, [&] {
-      return launch_zinv(n, fields({g}), fields({g}), 1, (long)n * n, tw, kEpiStore, e, st);
-    }));
-  }
+  e.reverse = 0;
+  e.deriv = 2;   // field 1 (g2): the z component
+  COLA_HIP(traced(p, kStZInv, st, [&] {
+    return launch_zinv(n, fields({g1, g2}), fields({g1, g2}), 2, (long)n * n, tw, kEpiStore, e, st);
+  }));
   e.deriv = 0;
+  e.reverse = 1;
   COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0}), 1, tw, st));
   COLA_HIP(traced(p, kStZInv, st, [&] {
     return launch_zinv(n, fields({g0}), fields({g0}), 1, (long)n * n, tw, kEpiStore, e, st);

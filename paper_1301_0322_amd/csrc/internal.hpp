@@ -42,7 +42,8 @@ struct EpiArgs {
   float* v;
   long comp_stride;
   int reverse;        // rows from the last block to the first (memory-side cache reuse)
-  int deriv;          // multiply mode k by i k before the transform (z derivative)
+  int deriv;          // bit f: field f's mode k is multiplied by i k before the transform (z derivative)
+  int nfields;        // set by launch_zinv
 };
 
 bool fft_size_supported(int n);

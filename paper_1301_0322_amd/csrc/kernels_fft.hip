@@ -139,12 +139,16 @@ __global__ __launch_bounds__(ZPencil<N>::T) void k_zinv(FieldPtrs in, FieldPtrs 
   constexpr int M = N / 2;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
-  const int f = blockIdx.y;
-  const long row0 = (long)(e.reverse ? gridDim.x - 1 - blockIdx.x : blockIdx.x) * P::NT;
+  // the fields' blocks alternate (field fastest), so fields written together by the
+  // previous pass are read together
+  const int nf = e.nfields;
+  const int f = (int)(blockIdx.x % nf);
+  const long blk = blockIdx.x / nf, nblk = gridDim.x / nf;
+  const long row0 = (e.reverse ? nblk - 1 - blk : blk) * P::NT;
   float2 q[P::UB][P::R1];
   P::load_b(q, in.p[f] + row0 * M, M);
   load_twiddles(stw, tw, N);
-  if (e.deriv) {
+  if ((e.deriv >> f) & 1) {
     // z derivative: mode k (0 <= k < n/2) times i k, before the Hermitian pairing
 #pragma unroll
     for (int u = 0; u < P::UB; ++u) {
@@ -474,7 +478,9 @@ static hipError_t zinv_t(FieldPtrs in, FieldPtrs out, int nf, long nrows, const 
                          EpiArgs e, hipStream_t st) {
   using P = ZPencil<N>;
   if (nrows % P::NT) return hipErrorInvalidValue;
-  dim3 grid(nrows / P::NT, nf);
+  if (nf < 1 || nf > kMaxFields) return hipErrorInvalidValue;
+  e.nfields = nf;
+  dim3 grid((unsigned)(nrows / P::NT * nf));
   if (epi == kEpiStore)
     hipLaunchKernelGGL((k_zinv<N, kEpiStore>), grid, dim3(P::T), 0, st, in, out, tw, e);
   else
