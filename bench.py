@@ -278,6 +278,7 @@ def main() -> int:
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-paper-mesh", action="store_true", help="skip the 256^3 / 768^3 PM step")
+    ap.add_argument("--no-analysis", action="store_true", help="skip timing cola_cross_power")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 256 MiB device to device once (a known-size kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -394,6 +395,21 @@ def main() -> int:
         "stages_per_run": per_run,
         "tuning": tuning,
     }
+    # density statistics of Section 3.1 on the final state: the run against itself
+    # through cola_cross_power (two deposits, two forward FFTs, shell sums)
+    out_stats = torch.zeros((6, nm // 2), dtype=torch.float64, device="cuda")
+    if not args.no_analysis:
+        plan.cross_power(p.s, p.s, out_stats, ws)
+        torch.cuda.synchronize()
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        for _ in range(args.steps):
+            plan.cross_power(p.s, p.s, out_stats, ws)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        out["analysis"] = {"call": "cola_cross_power (P_aa, P_bb, P_ab, rho, n_max per shell)",
+                           "ms": ea.elapsed_time(eb) / args.steps,
+                           "rho_min_shells_1_to_nm/2-1": float(out_stats[4, 1:].min().item())}
     if not args.no_ensemble:
         del ws
         torch.cuda.empty_cache()

@@ -131,6 +131,20 @@ int cola_init_2lpt(cola_plan plan, const float *w, const cola_particles *p, void
 /* Mean-1 CIC density of the particles at q + s: rho (device, nm^3 floats). */
 int cola_density(cola_plan plan, const float *s, float *rho, void *ws, void *stream);
 
+/* Density statistics of Section 3.1: the shell-averaged power spectra of the mean-1
+ * CIC densities of two particle sets at q + s_a and q + s_b (device, [3][np^3]
+ * floats each; s_b may be NULL for s_a alone), their cross spectrum, the
+ * cross-correlation coefficient rho(k) = P_ab / sqrt(P_aa P_bb) (the square root as
+ * in Appendix B) and n_max(k) = (2/3) rho / sqrt(1 - rho^2) of eq. (nmax).
+ * out (device, 6 * (nm/2) doubles) receives rows r = 0..5 of nm/2 shells
+ * s = round(|n|): mode count, P_aa, P_bb, P_ab, rho, n_max, with
+ * P = <|delta_k|^2> L^3 / nm^6 over all modes of the full grid (modes with kz > 0
+ * standing for their conjugates too).  Shell 0 (k = 0) is zero; shells are
+ * complete for s < nm/2 (the kz = nm/2 plane is not formed).  With s_b NULL rows
+ * 2..5 are zero.  The four workspace meshes are overwritten.  Errors:
+ * COLA_ERR_INVALID for a null s_a or out. */
+int cola_cross_power(cola_plan plan, const float *s_a, const float *s_b, double *out, void *ws, void *stream);
+
 /* PM force of eq. (eom) at scale factor a: acc = -(3/2) Om a d d^-2 delta
  * interpolated to each particle (device, [3][np^3] floats). */
 int cola_pm_force(cola_plan plan, const float *s, double a, float *acc, void *ws, void *stream);

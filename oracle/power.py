@@ -12,8 +12,15 @@ estimator details):
   round(|n|) = b, 1 <= b <= Nm/2;
 * no window deconvolution, no shot-noise subtraction.
 
+Section 3.1 also compares a model's density with the truth's through the
+cross-correlation coefficient rho(k) = P_x / sqrt(P_a P_b) (reading: the printed
+denominator lacks the square root, which the derivation in Appendix B has) and
+n_max(k) = (2/3) rho / sqrt(1 - rho^2), eq. (nmax).  P_x is the shell average of
+Re(delta_a,k delta_b,k^*) with the same weights as P.
+
 Parity unpinned against the paper (Fig. 2 is not recoverable); pinned by a
-single-mode closed form and Parseval's theorem in the tests.
+single-mode closed form, Parseval's theorem, identities of the cross spectrum and
+the n_max normalisation in the tests.
 """
 from __future__ import annotations
 
@@ -50,3 +57,47 @@ def power_of_positions(x, n_m: int, box: float):
     rho = cic_deposit_points(torch.remainder(x, box), n_m, box)
     delta = rho / rho.mean() - 1.0
     return power_from_delta(delta, box)
+
+
+def cross_power_from_delta(da: torch.Tensor, db: torch.Tensor, box: float):
+    """(P_a, P_b, P_x, n_b) for b = 1..N/2 of two real mesh fields on the same N^3 mesh,
+    P_x the shell average of Re(delta_a,k conj(delta_b,k))."""
+    n = da.shape[-1]
+    ka = rfft3(da.to(F64))
+    kb = rfft3(db.to(F64))
+    norm = box**3 / float(n) ** 6
+    pa = (ka.real**2 + ka.imag**2) * norm
+    pb = (kb.real**2 + kb.imag**2) * norm
+    px = (ka.real * kb.real + ka.imag * kb.imag) * norm
+    nx, ny, nz = mode_numbers(n)
+    shell = torch.round(torch.sqrt(nx * nx + ny * ny + nz * nz)).to(torch.int64)
+    mult = torch.full_like(pa, 2.0)
+    mult[..., 0] = 1.0
+    if n % 2 == 0:
+        mult[..., n // 2] = 1.0
+    nb = n // 2
+    shell = shell.expand_as(pa).reshape(-1)
+    mult = mult.reshape(-1)
+    sel = (shell >= 1) & (shell <= nb)
+
+    def shell_mean(v):
+        tot = torch.zeros(nb + 1, dtype=F64).index_add(0, shell[sel], (mult * v.reshape(-1))[sel])
+        return tot[1:]
+
+    cnt = torch.zeros(nb + 1, dtype=F64).index_add(0, shell[sel], mult[sel])[1:]
+    return shell_mean(pa) / cnt, shell_mean(pb) / cnt, shell_mean(px) / cnt, cnt
+
+
+def correlation(pa, pb, px):
+    """rho = P_x / sqrt(P_a P_b) and n_max = (2/3) rho / sqrt(1 - rho^2), eq. (nmax)."""
+    rho = px / torch.sqrt(pa * pb)
+    return rho, (2.0 / 3.0) * rho / torch.sqrt(1.0 - rho * rho)
+
+
+def cross_power_of_positions(xa, xb, n_m: int, box: float):
+    """(P_a, P_b, P_x, n_b) of two point sets, each deposited as in power_of_positions."""
+    def delta(x):
+        x = torch.as_tensor(x, dtype=F64).reshape(3, -1)
+        rho = cic_deposit_points(torch.remainder(x, box), n_m, box)
+        return rho / rho.mean() - 1.0
+    return cross_power_from_delta(delta(xa), delta(xb), box)

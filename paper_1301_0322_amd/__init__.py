@@ -49,6 +49,7 @@ _PROTOS = {
     "cola_noise": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
     "cola_init_2lpt": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP]),
     "cola_density": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "cola_cross_power": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "cola_pm_force": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP]),
     "cola_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ColaParticles), _VP, _VP]),
     "cola_finish": (ctypes.c_int, [_VP, ctypes.POINTER(ColaParticles), _VP, _VP, _VP, _VP]),
@@ -224,6 +225,12 @@ class Plan:
 
     def density(self, s, rho, ws, stream=None):
         _check("cola_density", lib().cola_density(self._c, _ptr(s), _ptr(rho), _ptr(ws), _stream(stream)))
+
+    def cross_power(self, s_a, s_b, out, ws, stream=None):
+        """cola_cross_power: out (float64, 6 x nm/2 on the device) receives the mode
+        count, P_aa, P_bb, P_ab, rho and n_max per shell; s_b may be None."""
+        _check("cola_cross_power", lib().cola_cross_power(self._c, _ptr(s_a), _ptr(s_b),
+                                                          _ptr(out), _ptr(ws), _stream(stream)))
 
     def pm_force(self, s, a: float, acc, ws, stream=None):
         _check("cola_pm_force", lib().cola_pm_force(self._c, _ptr(s), a, _ptr(acc), _ptr(ws),

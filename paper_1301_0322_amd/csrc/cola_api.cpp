@@ -53,13 +53,13 @@ enum Stage : int {
   kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStZFwd, kStYFwd, kStXPoisson,
   kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
   kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kStAdjKick, kStAdjDeposit, kStAdjFft, kStAdjGather,
-  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kStYInvPair, kNumStages
+  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kStYInvPair, kStAnalysis, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
   "bin_count", "bin_scan", "bin_scatter", "deposit", "fft_z_fwd", "fft_y_fwd",
   "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
   "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
-  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort", "fft_y_inv_pair"};
+  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort", "fft_y_inv_pair", "analysis"};
 
 // Trace levels: 1 records an event pair around every kernel launch, 2 only around
 // each whole COLA step of cola_run (stage run_step), so step times carry no
@@ -235,10 +235,8 @@ int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t
   return COLA_OK;
 }
 
-// The force mesh: g_d = (3/2) Om a irfft(i k_d delta_k / k^2), d = 0..2, in
-// ws[0 .. 3 nm^3) as three real nm^3 fields.
 // Poisson solve on the density in ws mesh 0: g_d = (3/2) Om a irfft(i k_d delta_k / k^2),
-// d = 0..2, left in the three ws meshes.
+// d = 0..2, left in ws meshes 0, 1, 2 as real nm^3 fields (mesh 3 is scratch).
 int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   const int n = p->cfg.nm;
   const long r = cube(n);
@@ -707,6 +705,45 @@ int cola_density(cola_plan p, const float* s, float* rho, void* ws, void* stream
   COLA_TRY(check_common(p, ws));
   if (!s || !rho) return COLA_ERR_INVALID;
   return deposit_into(p, s, rho, static_cast<float*>(ws), (hipStream_t)stream);
+}
+
+// Forward 3D transform of the real field in ws mesh m (in place, half spectrum).
+int fft_forward(cola_plan p, float* g, hipStream_t st) {
+  const int n = p->cfg.nm;
+  const long h = n / 2;
+  const float2* tw = p->d_tw_nm;
+  COLA_HIP(traced(p, kStZFwd, st,
+                  [&] { return launch_zfwd(n, g, reinterpret_cast<float2*>(g), (long)n * n, tw, st); }));
+  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g}), 1, tw, st));
+  // x: columns along x (stride n h) in tiles of kz at fixed y
+  return hip_status(traced(p, kStAnalysis, st, [&] {
+    return launch_col(n, -1, fields({g}), fields({g}), 1, n, h, (long)n * h, (int)h, tw, p->fft_width[1], st);
+  }));
+}
+
+int cola_cross_power(cola_plan p, const float* s_a, const float* s_b, double* out, void* ws_, void* stream) {
+  COLA_TRY(check_common(p, ws_));
+  if (!s_a || !out) return COLA_ERR_INVALID;
+  float* ws = static_cast<float*>(ws_);
+  hipStream_t st = (hipStream_t)stream;
+  const int n = p->cfg.nm;
+  const long r = cube(n);
+  float* ga = ws;
+  float* gb = ws + r;
+  COLA_TRY(deposit_into(p, s_a, ga, ws, st));
+  COLA_TRY(fft_forward(p, ga, st));
+  if (s_b) {
+    COLA_TRY(deposit_into(p, s_b, gb, ws, st));
+    COLA_TRY(fft_forward(p, gb, st));
+  }
+  // delta_k = rho_k / mean(rho) with mean 1 (particle mass (nm/np)^3); the k = 0 mode
+  // is not reported.  P = <|delta_k|^2> L^3 / nm^6.
+  const double norm = std::pow(p->cfg.box, 3) / std::pow((double)n, 6);
+  double* part = reinterpret_cast<double*>(ws + 2 * r);   // meshes 2 and 3
+  return hip_status(traced(p, kStAnalysis, st, [&] {
+    return launch_shell_stats(n, reinterpret_cast<const float2*>(ga), s_b ? reinterpret_cast<const float2*>(gb) : nullptr,
+                              part, r, norm, out, st);
+  }));
 }
 
 int cola_pm_force(cola_plan p, const float* s, double a, float* acc, void* ws_, void* stream) {

@@ -67,6 +67,12 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, int n_outer,
                       long outer_stride, long inner_stride, int ncols, const float2* tw, int width,
                       hipStream_t st, int reverse = 0);
+// Shell statistics of one or two half spectra (b may be null) into out[6][n/2]
+// (doubles, row r, shell s = round(|n|) for 1 <= s < n/2; s = 0 stays zero): mode
+// count, P_aa, P_bb, P_ab (sums / count * norm), rho and n_max.  part holds
+// part_doubles doubles of per-block partial sums (at least 2 n).
+hipError_t launch_shell_stats(int n, const float2* a, const float2* b, double* part, long part_doubles, double norm,
+                              double* out, hipStream_t st);
 // Inverse column pass of one field with two outputs: out_d = inverse transform of
 // i n X (n the signed mode number along the column) and out_p = inverse transform of
 // X.  The three buffers are distinct.

@@ -681,6 +681,103 @@ hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Shell statistics of two half spectra a, b ([x][y][kz], n/2 kz per row; the kz = n/2
+// plane is not stored, so shells s = round(|n|) with 1 <= s < n/2 are complete).
+// Per shell: the mode count and the sums of |a|^2, |b|^2 and Re(a conj b), each mode
+// with kz > 0 counted twice (it stands for its conjugate partner too).  The shell is
+// decided in integers.  Blocks accumulate in LDS (FP64 atomics) over a contiguous
+// range of elements and write partial sums; k_shell_reduce adds the partials block
+// by block in a fixed order and forms P, rho = P_ab / sqrt(P_aa P_bb) and
+// n_max = (2/3) rho / sqrt(1 - rho^2).
+// ---------------------------------------------------------------------------------
+constexpr int kShellThreads = 256;
+
+__device__ __forceinline__ int shell_of(int n2) {
+  int s = (int)sqrtf((float)n2);
+  while (s * s > n2) --s;
+  while ((s + 1) * (s + 1) <= n2) ++s;
+  return n2 > s * s + s ? s + 1 : s;   // round(sqrt(n2)): sqrt(n2) >= s + 1/2 iff n2 > s^2 + s
+}
+
+__global__ __launch_bounds__(kShellThreads) void k_shell_sums(int n, const float2* __restrict__ a,
+                                                              const float2* __restrict__ b, long chunk,
+                                                              double* __restrict__ part) {
+  extern __shared__ double acc[];   // [4][h]: count, aa, bb, ab
+  const int h = n / 2;
+  for (int i = threadIdx.x; i < 4 * h; i += kShellThreads) acc[i] = 0.0;
+  __syncthreads();
+  const long total = (long)n * n * h;
+  const long beg = (long)blockIdx.x * chunk;
+  const long end = beg + chunk < total ? beg + chunk : total;
+  for (long e = beg + threadIdx.x; e < end; e += kShellThreads) {
+    const int kz = (int)(e % h);
+    const long r = e / h;
+    const int y = (int)(r % n), x = (int)(r / n);
+    const int nx = x <= h ? x : x - n, ny = y <= h ? y : y - n;
+    const int sh = shell_of(nx * nx + ny * ny + kz * kz);
+    if (sh < 1 || sh >= h) continue;
+    const double w = kz > 0 ? 2.0 : 1.0;
+    const float2 va = a[e];
+    atomicAdd(&acc[sh], w);
+    atomicAdd(&acc[h + sh], w * ((double)va.x * va.x + (double)va.y * va.y));
+    if (b) {
+      const float2 vb = b[e];
+      atomicAdd(&acc[2 * h + sh], w * ((double)vb.x * vb.x + (double)vb.y * vb.y));
+      atomicAdd(&acc[3 * h + sh], w * ((double)va.x * vb.x + (double)va.y * vb.y));
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 4 * h; i += kShellThreads) part[(long)blockIdx.x * 4 * h + i] = acc[i];
+}
+
+__global__ __launch_bounds__(kShellThreads) void k_shell_reduce(int h, const double* __restrict__ part, int nblocks,
+                                                                double norm, int cross, double* __restrict__ out) {
+  const int sh = blockIdx.x * kShellThreads + threadIdx.x;
+  if (sh >= h) return;
+  double c = 0.0, aa = 0.0, bb = 0.0, ab = 0.0;
+  for (int k = 0; k < nblocks; ++k) {
+    const double* q = part + (long)k * 4 * h;
+    c += q[sh];
+    aa += q[h + sh];
+    bb += q[2 * h + sh];
+    ab += q[3 * h + sh];
+  }
+  double paa = 0.0, pbb = 0.0, pab = 0.0, rho = 0.0, nmax = 0.0;
+  if (c > 0.0) {
+    paa = aa / c * norm;
+    pbb = bb / c * norm;
+    pab = ab / c * norm;
+    if (cross && paa > 0.0 && pbb > 0.0) {
+      rho = pab / sqrt(paa * pbb);
+      nmax = (2.0 / 3.0) * rho / sqrt(fmax(1.0 - rho * rho, 0.0));
+    }
+  }
+  out[sh] = c;
+  out[h + sh] = paa;
+  out[2 * h + sh] = pbb;
+  out[3 * h + sh] = pab;
+  out[4 * h + sh] = rho;
+  out[5 * h + sh] = nmax;
+}
+
+hipError_t launch_shell_stats(int n, const float2* a, const float2* b, double* part, long part_doubles, double norm,
+                              double* out, hipStream_t st) {
+  if (n < 4 || n % 2 || !a || !part || !out) return hipErrorInvalidValue;
+  const int h = n / 2;
+  const long total = (long)n * n * h;
+  long nb = part_doubles / (4L * h);
+  nb = nb < 1024 ? nb : 1024;
+  if (nb < 1) return hipErrorInvalidValue;
+  const long chunk = (total + nb - 1) / nb;
+  nb = (total + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_shell_sums, dim3((unsigned)nb), dim3(kShellThreads), 4 * h * sizeof(double), st, n, a, b, chunk,
+                     part);
+  hipLaunchKernelGGL(k_shell_reduce, dim3((unsigned)((h + kShellThreads - 1) / kShellThreads)), dim3(kShellThreads), 0,
+                     st, h, part, (int)nb, norm, b != nullptr ? 1 : 0, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_col_pair(int n, const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
                            long inner_stride, int ncols, const float2* tw, int width, hipStream_t st, int reverse) {
   if (out_d == in || out_p == in || out_d == out_p) return hipErrorInvalidValue;

@@ -32,3 +32,76 @@ def test_mode_counts_cover_the_sphere():
     sh = torch.round(torch.sqrt(nx**2 + ny**2 + nz**2)).to(torch.int64)
     for b in range(1, n // 2 + 1):
         assert cnt[b - 1].item() == (sh == b).sum().item()
+
+
+def _fields(n=16, seed=3):
+    g = torch.Generator().manual_seed(seed)
+    return (torch.randn(n, n, n, generator=g, dtype=F64), torch.randn(n, n, n, generator=g, dtype=F64),
+            torch.randn(n, n, n, generator=g, dtype=F64))
+
+
+def test_cross_spectrum_identities():
+    a, b, c = _fields()
+    box = 50.0
+    pa, pb, px, cnt = power.cross_power_from_delta(a, b, box)
+    # the auto spectra agree with the single-field estimator
+    pa_ref, cnt_ref = power.power_from_delta(a, box)
+    assert torch.allclose(pa, pa_ref, rtol=1e-13) and torch.equal(cnt, cnt_ref)
+    # a field against itself, a positive and a negative multiple: rho = 1, 1, -1
+    for f, sign in ((a, 1.0), (2.5 * a, 1.0), (-0.7 * a, -1.0)):
+        qa, qb, qx, _ = power.cross_power_from_delta(a, f, box)
+        rho, _ = power.correlation(qa, qb, qx)
+        assert torch.allclose(rho, torch.full_like(rho, sign), atol=1e-12)
+    # bilinear in the second field, symmetric in the two
+    _, _, x_bc, _ = power.cross_power_from_delta(a, b + c, box)
+    _, _, x_c, _ = power.cross_power_from_delta(a, c, box)
+    assert torch.allclose(x_bc, px + x_c, rtol=1e-10, atol=1e-12)
+    _, _, x_ba, _ = power.cross_power_from_delta(b, a, box)
+    assert torch.allclose(x_ba, px, rtol=1e-13)
+    # Cauchy-Schwarz per shell
+    assert bool((px.abs() <= torch.sqrt(pa * pb) * (1 + 1e-12)).all())
+
+
+def test_independent_fields_are_uncorrelated():
+    # white noise fields: rho in each shell is a mean of n_b independent terms of
+    # zero mean, so |rho| stays within a few / sqrt(n_b)
+    a, b, _ = _fields(n=32, seed=11)
+    pa, pb, px, cnt = power.cross_power_from_delta(a, b, 1.0)
+    rho, _ = power.correlation(pa, pb, px)
+    sel = cnt >= 50
+    assert bool((rho[sel].abs() < 5.0 / torch.sqrt(cnt[sel])).all())
+
+
+def test_n_max_normalisation():
+    # Appendix B fixes the coefficient 2/3 so that n_max = 2 when the residual power
+    # P_eps = P_NL - R^2 P_M is 10% of P_NL; with R = P_x / P_M that is
+    # rho^2 = 1 - P_eps / P_NL = 0.9.  Build such a pair mode by mode:
+    # delta_M = delta_NL + eps with eps orthogonal to delta_NL in every mode.
+    n, box = 16, 1.0
+    a, _, _ = _fields(n=n, seed=5)
+    ka = torch.fft.rfftn(a)
+    # eps_k = i c sign(n_x) delta_k is Hermitian (a real field) and orthogonal per mode;
+    # modes with n_x = 0 or n_x = n/2 get eps = 0, so only shells free of them are exact
+    nx = torch.fft.fftfreq(n, d=1.0 / n, dtype=F64).round().view(n, 1, 1)
+    sgn = torch.sign(nx) * (nx.abs() != n // 2)
+    c = 1.0 / 3.0                     # P_eps / P_NL = c^2 = 1/9 where eps is non-zero
+    km = ka + 1j * c * sgn * ka
+    m = torch.fft.irfftn(km, s=(n, n, n))
+    pm_, pnl, px, _ = power.cross_power_from_delta(m, a, box)
+    rho, nmax = power.correlation(pm_, pnl, px)
+    # rho = 1 / sqrt(1 + c^2) = sqrt(0.9) on modes with eps; check the mode-level
+    # identity on the whole-box sums restricted to n_x != 0, n/2
+    w = (sgn != 0).expand(n, n, n // 2 + 1)
+    mult = torch.full((n, n, n // 2 + 1), 2.0, dtype=F64)
+    mult[..., 0] = 1.0
+    mult[..., n // 2] = 1.0
+    kmm = torch.fft.rfftn(m)
+    sx = (mult * (kmm * ka.conj()).real)[w].sum()
+    sm = (mult * kmm.abs() ** 2)[w].sum()
+    sa = (mult * ka.abs() ** 2)[w].sum()
+    r = sx / torch.sqrt(sm * sa)
+    assert r.item() == pytest.approx(math.sqrt(0.9), rel=1e-12)
+    _, nm = power.correlation(sm, sa, sx)
+    assert nm.item() == pytest.approx(2.0, rel=1e-11)
+    # per shell, rho lies between sqrt(0.9) (all modes with eps) and 1
+    assert bool(((rho >= math.sqrt(0.9) - 1e-12) & (rho <= 1 + 1e-12)).all())
