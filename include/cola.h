@@ -59,6 +59,9 @@ extern "C" {
 #define COLA_FLAG_KDK_STD 0x1u      /* standard COLA discretisation, eq. (KDKALCstd) */
 #define COLA_FLAG_NO_LPT_FRAME 0x2u /* plain PM leapfrog, eq. (KDKStd): s1 = s2 = 0 in the operators */
 #define COLA_FLAG_LOG_A_STEPS 0x4u  /* timesteps uniform in log a (Appendix A.2) instead of in a */
+#define COLA_FLAG_U1_DRIFT 0x8u     /* eq. (KDKALC) with u = 1 in the drift and u = a^nLPT in the kick (the
+                                       variant of the footnote on u(a), Appendix A.3.2); ignored with
+                                       COLA_FLAG_KDK_STD or COLA_FLAG_NO_LPT_FRAME */
 
 /* Run configuration (Section 2 and Appendix A.3).  Plain data, copied by
  * cola_plan_create. */

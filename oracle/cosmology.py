@@ -24,7 +24,9 @@ Paper passages followed:
   kick carries -(3/2) Om d d^-2 delta without the factor a_c, so with the force
   F = -(3/2) Om a_c d d^-2 delta the factor is again int (a/a_c)/Q da.
   ``Config.log_a_steps``: a_i uniform in log a (Appendix A.2), midpoints still
-  arithmetic (the choice stated there for small steps).
+  arithmetic (the choice stated there for small steps).  ``Config.u1_drift``: the
+  footnote's variant of eq. (KDKALC), u = A + B a^nLPT with B << A, i.e. u = 1 in the
+  drift (factor int 1/Q da) and u = a^nLPT in the kick.
 
 Readings of the variants: eq. (KDKALCstd) is printed with a minus sign in front of
 the kick integral while the bracket it multiplies is already the acceleration; read
@@ -63,6 +65,7 @@ class Config:
     n_lpt: float = -2.5
     scheme: str = "modified"   # "modified" eq. (KDKALC), "standard" eq. (KDKALCstd), "pm" eq. (KDKStd)
     log_a_steps: bool = False  # a_i uniform in log a instead of in a
+    u1_drift: bool = False     # "modified" with u = 1 in the drift (footnote on u(a), Appendix A.3.2)
 
     @property
     def omega_k(self) -> float:
@@ -207,7 +210,9 @@ def step_table(cfg: Config) -> StepTable:
         lo = a[0] if i == 0 else am[i - 1]
         hi = a[n] if i == n else am[i]
         alpha[i] = kick_factor_std(lo, hi, a[i], cfg) if std else kick_factor(lo, hi, a[i], cfg)
-    beta = np.array([drift_factor_std(a[i], a[i + 1], cfg) if std else drift_factor(a[i], a[i + 1], am[i], cfg)
+    # u = 1 in eq. (KDKALC)'s drift gives int 1/Q da, the standard drift factor
+    plain_drift = std or cfg.u1_drift
+    beta = np.array([drift_factor_std(a[i], a[i + 1], cfg) if plain_drift else drift_factor(a[i], a[i + 1], am[i], cfg)
                      for i in range(n)])
     g = growth(a, cfg)
     return StepTable(a=a, a_mid=am, alpha=alpha, beta=beta,

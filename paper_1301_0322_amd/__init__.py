@@ -19,6 +19,7 @@ COLA_OK = 0
 COLA_FLAG_KDK_STD = 0x1
 COLA_FLAG_NO_LPT_FRAME = 0x2
 COLA_FLAG_LOG_A_STEPS = 0x4
+COLA_FLAG_U1_DRIFT = 0x8
 
 SUPPORTED_SIZES = (16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024)
 STEP_TABLE_COLUMNS = ("a", "D1", "D2", "TD1", "TD2", "T2D1", "T2D2", "alpha", "beta",

@@ -122,7 +122,7 @@ int validate(const cola_config* c) {
   if (!(c->a_init > 0) || !(c->a_final > c->a_init)) return COLA_ERR_INVALID;
   if (c->n_steps < 1 || c->n_steps > 100000) return COLA_ERR_INVALID;
   if (c->n_lpt == 0.0 || !std::isfinite(c->n_lpt)) return COLA_ERR_INVALID;
-  if (c->flags & ~(uint32_t)(COLA_FLAG_KDK_STD | COLA_FLAG_NO_LPT_FRAME | COLA_FLAG_LOG_A_STEPS))
+  if (c->flags & ~(uint32_t)(COLA_FLAG_KDK_STD | COLA_FLAG_NO_LPT_FRAME | COLA_FLAG_LOG_A_STEPS | COLA_FLAG_U1_DRIFT))
     return COLA_ERR_INVALID;
   // E(a)^2 must stay positive on [a_init, a_final]
   const double ok = 1.0 - c->omega_m - c->omega_l;

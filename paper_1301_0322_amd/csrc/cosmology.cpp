@@ -163,8 +163,10 @@ std::vector<StepRow> build_step_table(const Cosmo& c, double a_init, double a_fi
     }
     if (i < n) {
       r.a_mid = am[i];
-      r.beta = (flags & (kFlagKdkStd | kFlagNoLpt)) ? c.int_1_over_q(a[i], a[i + 1])
-                                                     : c.int_u_over_q(a[i], a[i + 1]) / c.u(am[i]);
+      // eq. (KDKALC) drift int u/Q da / u(a_c); with u = 1 (the footnote's variant, kick
+      // unchanged) and in the standard schemes it is int 1/Q da
+      r.beta = (flags & (kFlagKdkStd | kFlagNoLpt | kFlagU1Drift)) ? c.int_1_over_q(a[i], a[i + 1])
+                                                                    : c.int_u_over_q(a[i], a[i + 1]) / c.u(am[i]);
     }
     r.force = 1.5 * c.omega_m * a[i];
   }

@@ -9,6 +9,7 @@ namespace cola {
 constexpr uint32_t kFlagKdkStd = 0x1u;
 constexpr uint32_t kFlagNoLpt = 0x2u;
 constexpr uint32_t kFlagLogA = 0x4u;
+constexpr uint32_t kFlagU1Drift = 0x8u;
 
 struct Growth {
   double d1 = 0, d2 = 0, td1 = 0, td2 = 0, t2d1 = 0, t2d2 = 0;

@@ -56,7 +56,7 @@ def test_workspace_size():
 
 def _oracle_scheme(flags: int) -> dict:
     """Oracle Config fields for the library's variant flags."""
-    out = {"log_a_steps": bool(flags & cola.COLA_FLAG_LOG_A_STEPS)}
+    out = {"log_a_steps": bool(flags & cola.COLA_FLAG_LOG_A_STEPS), "u1_drift": bool(flags & cola.COLA_FLAG_U1_DRIFT)}
     if flags & cola.COLA_FLAG_NO_LPT_FRAME:
         out["scheme"] = "pm"
     elif flags & cola.COLA_FLAG_KDK_STD:
@@ -69,7 +69,9 @@ def _oracle_scheme(flags: int) -> dict:
                                 {"flags": cola.COLA_FLAG_KDK_STD},
                                 {"flags": cola.COLA_FLAG_NO_LPT_FRAME, "n_steps": 7},
                                 {"flags": cola.COLA_FLAG_LOG_A_STEPS},
-                                {"flags": cola.COLA_FLAG_KDK_STD | cola.COLA_FLAG_LOG_A_STEPS, "a_init": 0.02}])
+                                {"flags": cola.COLA_FLAG_KDK_STD | cola.COLA_FLAG_LOG_A_STEPS, "a_init": 0.02},
+                                {"flags": cola.COLA_FLAG_U1_DRIFT},
+                                {"flags": cola.COLA_FLAG_U1_DRIFT | cola.COLA_FLAG_LOG_A_STEPS, "n_lpt": 1.5}])
 def test_host_step_table_matches_oracle(kw):
     cfg = cola.Config(**kw)
     with cola.Plan(cfg) as p:

@@ -30,12 +30,14 @@ def _ocfg(c: cola.Config) -> cosmo.Config:
         scheme = "standard"
     return cosmo.Config(np_side=c.np, nm_side=c.nm, box=c.box, omega_m=c.omega_m, omega_l=c.omega_l, h=c.h,
                         n_s=c.n_s, sigma8=c.sigma8, a_init=c.a_init, a_final=c.a_final, n_steps=c.n_steps,
-                        n_lpt=c.n_lpt, scheme=scheme, log_a_steps=bool(c.flags & cola.COLA_FLAG_LOG_A_STEPS))
+                        n_lpt=c.n_lpt, scheme=scheme, log_a_steps=bool(c.flags & cola.COLA_FLAG_LOG_A_STEPS),
+                        u1_drift=bool(c.flags & cola.COLA_FLAG_U1_DRIFT))
 
 
 _STD = cola.COLA_FLAG_KDK_STD
 _PM = cola.COLA_FLAG_NO_LPT_FRAME
 _LOG = cola.COLA_FLAG_LOG_A_STEPS
+_U1 = cola.COLA_FLAG_U1_DRIFT
 
 
 def test_noise_matches_oracle_generator():
@@ -136,7 +138,7 @@ def test_full_run_matches_oracle(seed):
     assert x.min() >= 0.0 and x.max() < cfg.box
 
 
-@pytest.mark.parametrize("flags", [_STD, _PM, _LOG, _STD | _LOG, _PM | _LOG])
+@pytest.mark.parametrize("flags", [_STD, _PM, _LOG, _STD | _LOG, _PM | _LOG, _U1, _U1 | _LOG])
 def test_variant_run_matches_oracle(flags):
     # eqs. (KDKALCstd), (KDKStd) and steps uniform in log a (Appendix A.2), same bars
     # as the default scheme.
@@ -155,6 +157,21 @@ def test_variant_run_matches_oracle(flags):
     pk_orc, _ = power.power_of_positions(torch.from_numpy(rx), cfg.nm, cfg.box)
     rel = (pk_gpu / pk_orc - 1.0).abs().max().item()
     assert rel <= 1e-4, rel
+
+
+@pytest.mark.parametrize("n_lpt,n_steps", [(-4.0, 10), (1.5, 10), (-1.0, 3)])
+def test_n_lpt_scan_points_match_oracle(n_lpt, n_steps):
+    # the points of an n_LPT scan (Appendix A.3.2 fits n_LPT by such scans): same bars
+    cfg = cola.Config(np=32, nm=64, n_lpt=n_lpt, n_steps=n_steps)
+    oc = _ocfg(cfg)
+    w = inputs.white_noise(32, 1301)
+    announce(f"run 32/64 n_lpt={n_lpt} n_steps={n_steps}")
+    x, v, p = cola.run(cfg, dev(w))
+    x, v = host(x), host(v)
+    rx, rv, rs = ocola.run(w.astype(np.float64), oc)
+    rx = rx.reshape(3, -1).numpy()
+    assert periodic_max_err(x, rx, cfg.box) <= 1e-3 * cfg.box
+    assert rel_l2(v, rv.reshape(3, -1).numpy()) < 1e-4
 
 
 @pytest.mark.parametrize("np_side,nm", [(32, 96), (16, 48)])

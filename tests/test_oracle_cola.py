@@ -111,8 +111,10 @@ def test_standard_cola_exact_in_linear_regime_and_pm_is_not():
     d_std = _linear_growth_deviation_cfg(32, 1, scheme="standard", n_steps=3)
     d_pm_a = _linear_growth_deviation_cfg(32, 1, scheme="pm", n_steps=10)
     d_pm_log = _linear_growth_deviation_cfg(32, 1, scheme="pm", n_steps=10, log_a_steps=True)
+    d_u1 = _linear_growth_deviation_cfg(32, 1, u1_drift=True, n_steps=3)
     assert abs(d_mod) < 0.04
     assert abs(d_std - d_mod) < 0.01
+    assert abs(d_u1 - d_mod) < 0.01
     assert abs(d_pm_a - d_mod) > 0.01
     assert abs(d_pm_log - d_mod) < 0.5 * abs(d_pm_a - d_mod)
 

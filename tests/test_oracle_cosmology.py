@@ -194,6 +194,29 @@ def test_standard_leapfrog_converges_at_second_order(log_a):
     assert 3.0 < errs[1] / errs[2] < 5.0
 
 
+def test_u1_drift_variant():
+    # The footnote's variant of eq. (KDKALC): u = 1 in the drift, u = a^nLPT in the
+    # kick.  EdS drift factor 2 (a_i^-1/2 - a_f^-1/2); kick factors unchanged; a
+    # residual acceleration c T[u](a) is still kicked exactly, and a constant velocity
+    # is now drifted exactly.
+    base = cosmo.Config(omega_m=1.0, omega_l=0.0, n_steps=5)
+    var = cosmo.Config(omega_m=1.0, omega_l=0.0, n_steps=5, u1_drift=True)
+    tb, tv = cosmo.step_table(base), cosmo.step_table(var)
+    np.testing.assert_array_equal(tb.alpha, tv.alpha)
+    a = tv.a
+    np.testing.assert_allclose(tv.beta, 2 * (a[:-1] ** -0.5 - a[1:] ** -0.5), rtol=1e-12)
+    cfg = cosmo.Config(n_steps=4, u1_drift=True)
+    table = cosmo.step_table(cfg)
+    c = 0.37
+    f = lambda x: c * float(cosmo.tu_of_a(x, cfg))
+    _, v_num = _run_scalar_kdk(f, 0.0, cfg, table)
+    assert v_num == pytest.approx(c * float(cosmo.u_of_a(cfg.a_final, cfg) - cosmo.u_of_a(cfg.a_init, cfg)),
+                                  rel=1e-12)
+    i1 = quad(lambda x: 1.0 / float(cosmo.q_of_a(x, cfg)), cfg.a_init, cfg.a_final, epsabs=0, epsrel=1e-13)[0]
+    s_num, _ = _run_scalar_kdk(lambda x: 0.0, 0.29, cfg, table)
+    assert s_num == pytest.approx(0.29 * i1, rel=1e-12)
+
+
 def test_lpt_velocity_cancels_at_start():
     # L-(a_0) applied to the 2LPT velocity gives v_res(a_0) = 0 (eq. Lops); the
     # T[D] used there must be the derivative of the D used for positions.
