@@ -58,8 +58,8 @@ constexpr int kClasses = 8;
 
 template <int TZ>
 struct TileDims {
-  static constexpr int EY = kTY + 1, EZ = TZ + 1;           // extents with the +1 halo (gather)
-  static constexpr int EXT = (kTX + 1) * EY * EZ;
+  static constexpr int EY = kTY, EZ = TZ + 1;               // staged core; rows padded by one word
+  static constexpr int EXT = kTX * EY * EZ;
   static constexpr int CORE = kTX * kTY * TZ;
   // threads per tile block: a tile holds 2 TZ particles on average at mesh ratio 2
   static constexpr int TT = TZ >= 64 ? 512 : kPartThreads;
@@ -365,19 +365,20 @@ __device__ __forceinline__ bool local_stencil(const Lattice& lat, const TileGeom
   return (unsigned)lc[0] < (unsigned)kTX && (unsigned)lc[1] < (unsigned)kTY && (unsigned)lc[2] < (unsigned)TZ;
 }
 
-// Copies NF mesh fields over the cells (x, y, z) of the tile with x <= 8, y <= 8
-// (periodic wrap) and z < TZ into LDS, field c at tile + c * EXT, row stride EZ.
-// Each staged row is one aligned run of TZ floats (whole cache lines): the z = TZ
-// plane, which would add a line per row, is not staged; the few particles whose
-// stencil reaches it read those corners from the mesh (corner_value), where the
-// next tile along z, staged at the same time on the same XCD, keeps them in L2.
+// Copies NF mesh fields over the tile's own cells (x < 8, y < 8, z < TZ) into LDS,
+// field c at tile + c * EXT, row stride EZ.  Each staged row is one aligned run of TZ
+// floats (whole cache lines).  The +1 planes along x, y and z that the CIC stencils
+// of the tile's upper-face particles reach are not staged: those corners are read from
+// the mesh (corner_value), where the neighbouring tiles, staged around the same time
+// on the same XCD, keep them in L2.  Staging only the core keeps the three-field tile
+// at 50 KB (three blocks per CU at depth 64) and reads each mesh cell from HBM once.
 // Every load of a lane is issued before its first LDS write, so a block has all of
 // its tile reads in flight at once.
 template <int TZ, int NF>
 __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const float* const* f, float* tile) {
   using D = TileDims<TZ>;
   constexpr int RQ = TZ / 4;                   // float4 per staged row
-  constexpr int NQ = (kTX + 1) * D::EY * RQ;   // staged float4
+  constexpr int NQ = kTX * D::EY * RQ;         // staged float4
   constexpr int IT = (NQ + D::TT - 1) / D::TT;
   float4 v[NF][IT];
 #pragma unroll
@@ -410,13 +411,13 @@ __device__ __forceinline__ void stage_fields(const TileGeom& t, int nm, const fl
   }
 }
 
-// Field value at tile-local cell (x, y, z), x, y <= 8, z <= TZ: LDS offset o for
-// z < TZ, else the mesh (the first plane of the next tile along z, wrapped).
+// Field value at tile-local cell (x, y, z), x, y <= 8, z <= TZ: LDS offset o inside the
+// staged core, else the mesh (wrapped).
 template <int TZ>
 __device__ __forceinline__ float corner_value(const float* tile_field, const float* mesh, int o, const TileGeom& t,
                                               int x, int y, int z, int nm) {
-  if (z < TZ) return tile_field[o];
-  int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + TZ;
+  if (x < kTX && y < kTY && z < TZ) return tile_field[o];
+  int gx = t.lo[0] + x, gy = t.lo[1] + y, gz = t.lo[2] + z;
   gx -= (gx >= nm) ? nm : 0;
   gy -= (gy >= nm) ? nm : 0;
   gz -= (gz >= nm) ? nm : 0;
@@ -609,7 +610,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_tiles(Lattice lat, 
           const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
 #pragma unroll
           for (int d = 0; d < 3; ++d)
-            f[d] += w0 * tile[d * D::EXT + o] +
+            f[d] += w0 * corner_value<TZ>(tile + d * D::EXT, gf[d], o, T_, lc[0] + a, lc[1] + b, lc[2], lat.nm) +
                     w1 * corner_value<TZ>(tile + d * D::EXT, gf[d], o + 1, T_, lc[0] + a, lc[1] + b, lc[2] + 1, lat.nm);
         }
     }
@@ -813,7 +814,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
           const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
 #pragma unroll
           for (int d = 0; d < 3; ++d)
-            f[d] += w0 * tile[d * D::EXT + o] +
+            f[d] += w0 * corner_value<TZ>(tile + d * D::EXT, gf[d], o, T_, lc[0] + a, lc[1] + b, lc[2], lat.nm) +
                     w1 * corner_value<TZ>(tile + d * D::EXT, gf[d], o + 1, T_, lc[0] + a, lc[1] + b, lc[2] + 1, lat.nm);
         }
     }
