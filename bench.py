@@ -207,13 +207,14 @@ def bench_ensemble(stream) -> dict:
             "sequential_particle_steps_per_s": work / (t_seq * 1e-3), "speedup": t_seq / t_graph}
 
 
-def bench_paper_mesh(steps: int) -> dict:
-    """The in-run PM step at the paper's 3x mesh (256^3 particles on 768^3 cells)."""
+def bench_paper_mesh(steps: int, config: str = "c1_paper_mesh") -> dict:
+    """The in-run PM step of another configuration: the paper's 3x mesh (256^3
+    particles on 768^3 cells) or the large box (512^3 on 1024^3, 400 Mpc/h)."""
     import torch
 
     import paper_1301_0322_amd as cola
 
-    np_side, nm, box, seed, desc = CONFIGS["c1_paper_mesh"]
+    np_side, nm, box, seed, desc = CONFIGS[config]
     cfg = cola.Config(np=np_side, nm=nm, box=box)
     with cola.Plan(cfg) as plan:
         ws = plan.workspace()
@@ -277,7 +278,7 @@ def main() -> int:
     ap.add_argument("--no-ensemble", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--no-paper-mesh", action="store_true", help="skip the 256^3 / 768^3 PM step")
+    ap.add_argument("--no-paper-mesh", action="store_true", help="skip the 256^3 / 768^3 and 512^3 / 1024^3 PM steps")
     ap.add_argument("--no-analysis", action="store_true", help="skip timing cola_cross_power")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 256 MiB device to device once (a known-size kernel for HBM byte counters)")
@@ -423,6 +424,8 @@ def main() -> int:
             del ws
         torch.cuda.empty_cache()
         out["paper_mesh"] = bench_paper_mesh(args.steps)
+        torch.cuda.empty_cache()
+        out["c2"] = bench_paper_mesh(args.steps, "c2")
         torch.cuda.empty_cache()
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")

@@ -43,7 +43,7 @@ using ZHPencil = Pencil<N / 2, floor_pow2(min_i(z_rows<N / 2>(), pmax(1, 128 / (
 
 // A column width is usable when it divides n/2, the LDS exchange fits in kColLdsMax
 // and the block stays within 1024 threads.
-constexpr size_t kColLdsMax = 104 * 1024;
+constexpr size_t kColLdsMax = 144 * 1024;
 template <int N, int B>
 constexpr bool col_ok() {
   return B >= 2 && B <= pow2_factor(N / 2) && B * (N / pencil_r2(N)) <= 1024 &&
@@ -595,7 +595,8 @@ static hipError_t xmul_t(int mode, const float2* in, FieldPtrs out, int nout, Mu
 template <int N>
 static hipError_t xmul_adj_t(int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
                              hipStream_t st) {
-  constexpr int B = xmul_width<N>();
+  // the transposed pass holds three inputs: 16 columns of 1024 would spill
+  constexpr int B = (N >= 1024 && xmul_width<N>() > 8) ? 8 : xmul_width<N>();
   constexpr int T = Pencil<N, B, false>::T;
   if (mode != kMulGrad && mode != kMulLpt1) return hipErrorInvalidValue;
   if (mode == kMulGrad ? nin != 3 : (nin < 1 || nin > kMaxFields)) return hipErrorInvalidValue;

@@ -213,6 +213,28 @@ def test_paper_mesh_full_size_run_properties():
     assert np.abs(vres.astype(np.float64).sum(axis=1)).max() < 1e-4 * np.abs(vres).sum() / 3
 
 
+def test_large_box_run_properties():
+    """512^3 particles on the 1024^3 mesh in 400 Mpc/h: momentum and range invariants."""
+    cfg = cola.Config(np=512, nm=1024, box=400.0)
+    announce("run 512/1024")
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        w = torch.empty(512**3, dtype=torch.float32, device="cuda")
+        plan.noise(1303, w)
+        p = cola.Particles.empty(512)
+        x = torch.empty((3, 512**3), dtype=torch.float32, device="cuda")
+        v = torch.empty_like(x)
+        plan.run(w, p, x, v, ws)
+        torch.cuda.synchronize()
+        ok = bool(torch.isfinite(x).all()) and x.min().item() >= 0.0 and x.max().item() < cfg.box
+        vd = p.v.double()
+        mom = (vd.sum(dim=1).abs().max() / (vd.abs().sum() / 3)).item()
+        del ws, w, p, x, v, vd
+        torch.cuda.empty_cache()
+    assert ok
+    assert mom < 1e-4
+
+
 @pytest.mark.parametrize("flags", [0, _PM | _LOG])
 def test_step_by_step_equals_run(flags):
     cfg = cola.Config(np=16, nm=32, flags=flags)
