@@ -50,10 +50,11 @@ __global__ __launch_bounds__(kPartThreads) void k_fill(float4* p, long n4, float
 //               lower neighbours that reach into it, accumulated in an LDS tile of
 //               exactly the tile's cells, which are then written with plain stores:
 //               every cell has one writer and no halo needs merging;
-//   gather      per tile: the three force meshes over tile + 1 read once into LDS,
-//               then every particle of the tile reads its 8 corners there.
+//   gather      per tile: the three force meshes over the tile's cells read once
+//               into LDS; every particle of the tile reads its 8 corners there (the
+//               corners past the tile's upper faces through L2).
 // ---------------------------------------------------------------------------------
-constexpr int kTX = 8, kTY = 8;   // tile cells along x and y; tz (8, 16 or 32) is a template parameter
+constexpr int kTX = 8, kTY = 8;   // tile cells along x and y; tz (8, 16, 32 or 64) is a template parameter
 constexpr int kClasses = 8;
 
 template <int TZ>
