@@ -136,9 +136,11 @@ struct BinBuffers {
 __host__ __device__ inline int heavy_min_of(long npart, int heavy_cap) {
   return (int)((npart + heavy_cap - 1) / heavy_cap);
 }
-// Tile depth: the largest of 8, 16, 32, 64 (<= tz_max) dividing nm (64 by default:
-// deeper tiles stage fewer halo cells per particle).
-Bins make_bins(int nm, int tz_max = 64);
+// Tile depth: the largest of 8, 16, 32, 64 (<= tz_max) dividing nm.  32 by default:
+// with the force tiles staged without halo, 8 x 8 x 32 tiles (25 KB of LDS, 256
+// threads) keep more blocks resident than 8 x 8 x 64 and measure as fast or faster at
+// every mesh size benchmarked; the autotuner can pick any depth per plan.
+Bins make_bins(int nm, int tz_max = 32);
 size_t bin_workspace_bytes(long npart, const Bins& b);
 BinBuffers carve_bins(void* base, long npart, const Bins& b);
 
