@@ -77,3 +77,10 @@ def test_cross_power_of_run_against_itself():
     assert np.abs(same[4, 1:] - 1.0).max() < 1e-6
     assert np.all(np.abs(diff[3, 1:]) <= np.sqrt(diff[1, 1:] * diff[2, 1:]) * (1 + 1e-9))
     assert diff[4, 1:].max() < 1.0 and diff[4, 1] > 0.9
+
+
+def test_cross_power_rejects_missing_input():
+    with cola.Plan(cola.Config(np=16, nm=32)) as plan:
+        out = torch.zeros((6, 16), dtype=torch.float64, device="cuda")
+        with pytest.raises(cola.ColaError):
+            plan.cross_power(None, None, out, plan.workspace())
