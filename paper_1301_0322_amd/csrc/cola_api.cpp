@@ -828,12 +828,14 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
       k.box = (float)p->cfg.box;
       g.s = q->s;
       g.v = q->v;
+      g.s1 = q->s1;
+      g.s2 = q->s2;
       g.out_a = x_out;
       g.out_b = v_out;
       const SortedState out = sorted_state(p, ws, which);
       COLA_HIP(traced(p, kStFinish, st,
                       [&] { return launch_gather_sorted(lat, b, src, out, bb, kGatherFinish, g, k, st); }));
-      COLA_HIP(traced(p, kStUnsort, st, [&] { return launch_unsort(lat, out, g, st); }));
+      COLA_HIP(traced(p, kStUnsort, st, [&] { return launch_unsort(lat, out, g, k, st); }));
     }
   }
   return COLA_OK;

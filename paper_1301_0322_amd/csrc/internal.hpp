@@ -202,14 +202,15 @@ struct SortedState {
 // Gather + kick over the tile lists bb.idx (slots of src).  kGatherKickDrift writes
 // the kicked and drifted record of list position j to slot j of the packed dst
 // (ordered by this step's tiles) and bins it for the next step (bb.count_next,
-// bb.key_rank by dst slot); kGatherFinish packs the final s, v, x and v_phys of slot j
-// into float4 j, n + j, 2n + j of dst.s (a packed block) and sets
-// dst.lag[Lagrangian index] = j, for launch_unsort.
+// bb.key_rank by dst slot); kGatherFinish writes s and the kicked v of list position
+// j as float4 j of dst.s (s.x s.y s.z v.x) and float2 j of dst.s + 4n (v.y v.z), and
+// sets dst.lag[Lagrangian index] = j, for launch_unsort.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st);
-// Lagrangian order from a kGatherFinish output w: a.s, a.v, a.out_a, a.out_b take
-// s, v, x, v_phys.
-hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t st);
+// Lagrangian order from a kGatherFinish output w: a.s, a.v take s and v; a.out_a
+// x = (q + s) mod L (k.box); a.out_b v_phys = v + k.td1 a.s1 + k.td2 a.s2, the L+ of
+// the closing step (a.s1, a.s2 the caller's arrays).
+hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, KickArgs k, hipStream_t st);
 
 // Adjoint kernels.
 struct AdjGatherArgs {

@@ -820,7 +820,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
         }
     }
     float snew[3] = {r.s[0], r.s[1], r.s[2]};
-    float vf[3], vp[3], xo[3];
+    float vf[3];
     if (in) {
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
@@ -831,13 +831,6 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
           vf[d] = v;
         } else {
           vf[d] = v;
-          vp[d] = v + k.td1 * a1 + k.td2 * a2;
-          int li[3];
-          lag_index(lat, r.lag, li);
-          float x = (float)li[d] * (k.box / (float)lat.np) + r.s[d];
-          x = x - k.box * floorf(x / k.box);
-          if (x >= k.box) x -= k.box;
-          xo[d] = x;
         }
       }
       if constexpr (MODE == kGatherKickDrift) {
@@ -848,13 +841,11 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
         dst.lag[j] = (int)r.lag;
       }
       if constexpr (MODE == kGatherFinish) {
-        // finish: s, v, x = (q + s) mod L and v_phys packed in three float4 per
-        // particle, in this step's tile order, and the slot of every Lagrangian index
-        // in dst.lag, for k_unsort
-        float4* o4 = reinterpret_cast<float4*>(dst.s);
-        o4[j] = make_float4(r.s[0], r.s[1], r.s[2], vf[0]);
-        o4[n + j] = make_float4(vf[1], vf[2], xo[0], xo[1]);
-        o4[2 * n + j] = make_float4(xo[2], vp[0], vp[1], vp[2]);
+        // finish: s and the kicked v, in this step's tile order, as a float4 plane
+        // (s.x s.y s.z v.x) and a float2 plane (v.y v.z), and the slot of every
+        // Lagrangian index in dst.lag, for k_unsort (which forms x and v_phys)
+        reinterpret_cast<float4*>(dst.s)[j] = make_float4(r.s[0], r.s[1], r.s[2], vf[0]);
+        reinterpret_cast<float2*>(dst.s + 4 * n)[j] = make_float2(vf[1], vf[2]);
         dst.lag[r.lag] = j;
       }
     }
@@ -1070,12 +1061,16 @@ hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedStat
   return hipGetLastError();
 }
 
-// Lagrangian order from the finish output: particle p takes slot inv[p] of the
-// packed tile-ordered copy (three float4 per slot: s, v, x, v_phys).  A block covers a
-// 4 x 4 x 16 block of the Lagrangian grid (when np allows), whose particles sit in a
-// few neighbouring tiles, so its scattered 16-byte reads stay local; its writes are
+// Lagrangian order from the finish output: particle p takes s and v from slot inv[p]
+// of the tile-ordered finish copy, then L+(a_n) (eq. Lops): v_phys = v + T[D1] s1 +
+// T[D2] s2 (k.td1, k.td2; s1, s2 from the caller's arrays, read in order) and
+// x = (q + s) mod L.  Only 24 bytes per particle are read out of order.  A block
+// covers a 4 x 4 x 16 block of the Lagrangian grid (when np allows), whose particles
+// sit in a few neighbouring tiles, so its scattered reads stay local; its writes are
 // runs of 16 consecutive elements.
-__global__ __launch_bounds__(kPartThreads) void k_unsort(int np, long n, SortedState w, GatherArgs g) {
+__global__ __launch_bounds__(kPartThreads) void k_unsort(Lattice lat, SortedState w, GatherArgs g, KickArgs k) {
+  const int np = lat.np;
+  const long n = lat.npart;
   long p;
   if (np % 16 == 0) {
     const int nbk = np / 16, nbj = np / 4;
@@ -1088,24 +1083,25 @@ __global__ __launch_bounds__(kPartThreads) void k_unsort(int np, long n, SortedS
   }
   if (p >= n) return;
   const long j = w.lag[p];
-  const float4* o4 = reinterpret_cast<const float4*>(w.s);
-  const float4 a = o4[j], b = o4[n + j], c = o4[2 * n + j];
-  g.s[p] = a.x;
-  g.s[n + p] = a.y;
-  g.s[2 * n + p] = a.z;
-  g.v[p] = a.w;
-  g.v[n + p] = b.x;
-  g.v[2 * n + p] = b.y;
-  g.out_a[p] = b.z;
-  g.out_a[n + p] = b.w;
-  g.out_a[2 * n + p] = c.x;
-  g.out_b[p] = c.y;
-  g.out_b[n + p] = c.z;
-  g.out_b[2 * n + p] = c.w;
+  const float4 a = reinterpret_cast<const float4*>(w.s)[j];
+  const float2 b = reinterpret_cast<const float2*>(w.s + 4 * n)[j];
+  const float sv[3] = {a.x, a.y, a.z}, vv[3] = {a.w, b.x, b.y};
+  int li[3];
+  lag_index(lat, (unsigned)p, li);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g.s[d * n + p] = sv[d];
+    g.v[d * n + p] = vv[d];
+    g.out_b[d * n + p] = vv[d] + k.td1 * g.s1[d * n + p] + k.td2 * g.s2[d * n + p];
+    float x = (float)li[d] * (k.box / (float)np) + sv[d];
+    x = x - k.box * floorf(x / k.box);
+    if (x >= k.box) x -= k.box;
+    g.out_a[d * n + p] = x;
+  }
 }
 
-hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, hipStream_t st) {
-  hipLaunchKernelGGL(k_unsort, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat.np, lat.npart, w, a);
+hipError_t launch_unsort(Lattice lat, SortedState w, GatherArgs a, KickArgs k, hipStream_t st) {
+  hipLaunchKernelGGL(k_unsort, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat, w, a, k);
   return hipGetLastError();
 }
 
