@@ -460,11 +460,10 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
     COLA_TRY(pm_mesh(p, s_i, row.a, ws, st));
     // nu_d = mass-weighted CIC deposit of mu_d = lam_v_d
     const BinBuffers bb = bin_buffers(p, ws);
-    for (int d = 0; d < 3; ++d) {
-      COLA_HIP(traced(p, kStAdjDeposit, st, [&] {
-        return launch_deposit(lat, b, s_i, bb, L.amesh[d], mass, st, L.lam_v + d * n);
-      }));
-    }
+    // the three components in one particle walk (amesh[d] = amesh[0] + d nm^3)
+    COLA_HIP(traced(p, kStAdjDeposit, st, [&] {
+      return launch_deposit3(lat, b, s_i, bb, L.amesh[0], mass, L.lam_v, st);
+    }));
     // rbar = sum_d K_d^T nu_d (conjugate multiplier), into amesh[0]
     const float2* tw = p->d_tw_nm;
     COLA_TRY(fwd_zy(p, kStAdjFft, nm, {L.amesh[0], L.amesh[1], L.amesh[2]}, tw, st));

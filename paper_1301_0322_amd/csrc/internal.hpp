@@ -157,6 +157,10 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
 // particle carries mass * weight.
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
                           hipStream_t st, const float* weight = nullptr, const int* lag = nullptr);
+// Three weighted deposits in one particle walk: rho + c nm^3 receives the CIC deposit
+// of mass * weight[c n + Lagrangian index], c = 0..2 (s SoA in Lagrangian order).
+hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
+                           const float* weight, hipStream_t st);
 
 struct KickArgs {
   float alpha;                 // kick factor

@@ -440,7 +440,9 @@ __device__ __forceinline__ float corner_value(const float* tile_field, const flo
 // s is SoA [3][np^3] in Lagrangian order.  weight is indexed by Lagrangian index.
 constexpr int kDepRanges = 20;
 
-template <int TZ, class ACC>
+// NW weight planes (weighted deposits): NW = 1 deposits mass * weight[lag]; NW = 3
+// deposits the three planes weight[c n + lag] into rho + c nm^3 in one particle walk.
+template <int TZ, class ACC, int NW = 1>
 __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat, Bins bins, const float* __restrict__ s,
                                                                 const int* __restrict__ lag,
                                                                 const int* __restrict__ idx,
@@ -448,12 +450,13 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
                                                                 const int* __restrict__ heavy, float* __restrict__ rho,
                                                                 float mass, const float* __restrict__ weight) {
   using D = TileDims<TZ>;
-  __shared__ ACC tile[D::CORE];
+  static_assert(NW == 1 || NW == 3, "one or three weight planes");
+  __shared__ ACC tile[NW * D::CORE];
   __shared__ int rbeg[kDepRanges], rpre[kDepRanges + 1], rmask[kDepRanges];
   TileGeom g;
   bool listed;
   if (!tile_geom<TZ>(bins, heavy, g, listed)) return;
-  for (int i = threadIdx.x; i < D::CORE; i += D::TT) tile[i] = 0;
+  for (int i = threadIdx.x; i < NW * D::CORE; i += D::TT) tile[i] = 0;
   if (threadIdx.x < 64) {
     // lane r < 20 describes range r: r = 0 own tile, then the (mask, class) pairs
     const int lane = threadIdx.x;
@@ -547,7 +550,9 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
       const int rx = (int)((unsigned)st.c[0] % kTX) - ((msk[u] & 1) ? kTX : 0);
       const int ry = (int)((unsigned)st.c[1] % kTY) - ((msk[u] & 2) ? kTY : 0);
       const int rz = (int)((unsigned)st.c[2] % TZ) - ((msk[u] & 4) ? TZ : 0);
-      const float mw = weight ? mass * weight[lg[u]] : mass;
+      float mw[NW];
+#pragma unroll
+      for (int c = 0; c < NW; ++c) mw[c] = weight ? mass * weight[c * lat.npart + lg[u]] : mass;
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int x = rx + a;
@@ -556,10 +561,13 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
         for (int b = 0; b < 2; ++b) {
           const int y = ry + b;
           if ((unsigned)y >= (unsigned)kTY) continue;
-          const float wab = mw * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
-          ACC* row = tile + (x * kTY + y) * TZ;
-          if ((unsigned)rz < (unsigned)TZ) tile_add(row + rz, wab * (1.f - st.f[2]));
-          if ((unsigned)(rz + 1) < (unsigned)TZ) tile_add(row + rz + 1, wab * st.f[2]);
+#pragma unroll
+          for (int c = 0; c < NW; ++c) {
+            const float wab = mw[c] * (a ? st.f[0] : 1.f - st.f[0]) * (b ? st.f[1] : 1.f - st.f[1]);
+            ACC* row = tile + c * D::CORE + (x * kTY + y) * TZ;
+            if ((unsigned)rz < (unsigned)TZ) tile_add(row + rz, wab * (1.f - st.f[2]));
+            if ((unsigned)(rz + 1) < (unsigned)TZ) tile_add(row + rz + 1, wab * st.f[2]);
+          }
         }
       }
     }
@@ -568,7 +576,9 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
   const long nm = lat.nm;
   for (int i = threadIdx.x; i < D::CORE; i += D::TT) {
     const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
-    rho[((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z] = tile_value(tile[i]);
+    const long cell = ((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z;
+#pragma unroll
+    for (int c = 0; c < NW; ++c) rho[c * nm * nm * nm + cell] = tile_value(tile[c * D::CORE + i]);
   }
 }
 
@@ -999,6 +1009,15 @@ hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t s
 hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
   hipLaunchKernelGGL(k_bin_scatter, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat.npart, bb.key_rank,
                      bb.offset, bb.idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
+                           const float* weight, hipStream_t st) {
+  if (!weight) return hipErrorInvalidValue;
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float, 3>), dim3(tile_blocks(b)),
+                                            dim3(TileDims<TZ>::TT), 0, st, lat, b, s, nullptr, bb.idx, bb.offset,
+                                            bb.heavy, rho, mass, weight))
   return hipGetLastError();
 }
 
