@@ -311,7 +311,8 @@ def main() -> int:
         plan.init_2lpt(w, p, ws)
         plan.autotune(p, None)
         ws = plan.workspace()
-    tuning = dict(zip(("y_width", "x_width", "bin_depth"), plan.get_tuning()))
+    # widths of 0 mean the built-in default (the widest column tile whose LDS fits)
+    tuning = {k: (v if v else "default") for k, v in zip(("y_width", "x_width", "bin_depth"), plan.get_tuning())}
     tuning["source"] = "autotuned" if args.autotune and not args.no_autotune else "plan defaults"
 
     for _ in range(args.warmup):
