@@ -165,9 +165,10 @@ int cola_finish(cola_plan plan, const cola_particles *p, float *x_out, float *v_
 
 /* Whole run: cola_init_2lpt, then the n_steps COLA steps and the closing kick of
  * cola_step / cola_finish.  Internally the particle state is kept in workspace
- * copies sorted by mesh tile between force evaluations (same arithmetic, order of
- * FP32 summation in the deposit aside); on return p holds the final s, v_res (in
- * Lagrangian order) and the unchanged s1, s2. */
+ * copies sorted by mesh tile between force evaluations, with the same arithmetic:
+ * the results equal those of the step-by-step calls bit for bit (the mass deposit
+ * sums 64-bit fixed point, independent of particle order).  On return p holds the
+ * final s, v_res (in Lagrangian order) and the unchanged s1, s2. */
 int cola_run(cola_plan plan, const float *w, const cola_particles *p, float *x_out, float *v_out, void *ws,
              void *stream);
 
