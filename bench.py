@@ -115,6 +115,33 @@ def read_traffic(stage: str, workload: str):
         return None
 
 
+# kernel of each timed stage, by bin depth, as rocprofv3 names it
+STAGE_KERNEL = {"gather_kick_drift": "k_gather_sorted<{tz}, 1>",
+                "deposit": "k_deposit_tiles<{tz}, unsigned long long, 1>"}
+
+
+def read_profile_avg(stage: str, workload: str, tz: int):
+    """Mean kernel duration (ms) of a stage's kernel in the committed rocprofv3
+    kernel-trace summary, if it is for this kernel source, workload and bin depth."""
+    path = os.path.join(ROOT, "profiles", f"kernel_trace_cola_run_{workload}.txt")
+    if stage not in STAGE_KERNEL or not os.path.exists(path):
+        return None
+    name = STAGE_KERNEL[stage].format(tz=tz)
+    digest = None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("source_digest:"):
+                digest = line.split(":", 1)[1].strip()
+            elif line.startswith(name + " ") and digest == csrc_digest():
+                cols = line[len(name):].split()
+                try:
+                    return {"file": os.path.relpath(path, ROOT), "kernel": name, "calls": int(cols[0]),
+                            "avg_ms": float(cols[1]) * 1e-3}
+                except (IndexError, ValueError):
+                    return None
+    return None
+
+
 def cpu_baseline(np_side: int, nm: int, box: float, seed: int) -> dict:
     """The FP64 oracle on one COLA step of the same workload (ICs untimed)."""
     import numpy as np
@@ -368,6 +395,7 @@ def main() -> int:
     achieved = dom_bytes / (dom_ms_launch * 1e-3) / 1e9
     workload = f"{args.config}"
     traffic = read_traffic(dom, workload)
+    profile = read_profile_avg(dom, workload, plan.get_tuning()[2])
     b_alg = b_alg_step(np_side, nm)
 
     out = {
@@ -388,7 +416,8 @@ def main() -> int:
                    "np": np_side, "nm": nm, "box_mpc_h": box, "n_steps": cfg.n_steps},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms_launch},
+                     "algorithmic_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms_launch,
+                     "rocprofv3": profile},
         "pm_step": {"ms": pm_step_ms, "particle_steps_per_s": np_side**3 / (pm_step_ms * 1e-3),
                     "b_alg_bytes": b_alg, "hbm_frac": b_alg / (pm_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                     "b_alg_three_chains_bytes": b_alg_three_chains(np_side, nm),

@@ -25,3 +25,14 @@ def test_step_bytes_add_up():
         # three independent inverse chains would move 16 C more
         c = nm * nm * (nm // 2 + 1)
         assert bench.b_alg_three_chains(np_side, nm) - bench.b_alg_step(np_side, nm) == 16 * c
+
+
+def test_committed_profiles_cover_the_current_sources():
+    # the roofline's traffic and rocprofv3 mean come from the committed summaries only
+    # when those were taken on the current kernel sources, for the benchmarked bin depth
+    traffic = bench.read_traffic("gather_kick_drift", "c1")
+    prof = bench.read_profile_avg("gather_kick_drift", "c1", 32)
+    assert traffic is not None and traffic > bench.stage_bytes(256, 512)["gather_kick_drift"]
+    assert prof is not None and prof["kernel"] == "k_gather_sorted<32, 1>" and 0.1 < prof["avg_ms"] < 10
+    assert bench.read_profile_avg("gather_kick_drift", "c1", 64) is None
+    assert bench.read_profile_avg("no_such_stage", "c1", 32) is None
