@@ -96,7 +96,8 @@ def test_pm_force_full_size_matches_oracle():
 
 @pytest.mark.parametrize("np_side,nm", [(32, 64), (128, 256)])
 def test_fft_tile_shapes_agree(np_side, nm):
-    """Every valid strided-pass tile width gives the same force (up to rounding)."""
+    """Every valid strided-pass tile width gives the same force bit for bit: the width
+    sets how many columns one block transforms, not the arithmetic of a column."""
     s = dev(_state(np_side, 100.0, 9, 2.0))
     outs = {}
     for wy, wx in [(0, 0), (4, 4), (8, 8), (16, 16), (8, 16), (16, 8)]:
@@ -109,7 +110,7 @@ def test_fft_tile_shapes_agree(np_side, nm):
             outs[(wy, wx)] = host(acc)
     ref = outs[(0, 0)]
     for key, got in outs.items():
-        assert rel_l2(got, ref) < 2e-6, key
+        assert np.array_equal(got, ref), (key, rel_l2(got, ref))
 
 
 def test_fft_tile_rejects_invalid_width():
