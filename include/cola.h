@@ -212,14 +212,16 @@ int cola_fft_c2r(cola_plan plan, int32_t n, const float *in, float *out, void *s
  * are identical for every valid shape).  pass 0 = the y passes, 1 = the x pass
  * with the Poisson multiplier; width = columns per tile, one of 4, 8, 16, or 0 for
  * the built-in default.  COLA_ERR_UNSUPPORTED_SIZE if the width does not divide
- * nm/2 or the tile would exceed 64 KB of LDS.  Host-only. */
+ * nm/2 or the tile's LDS exchange would exceed 144 KB.  Host-only. */
 int cola_plan_set_fft_tile(cola_plan plan, int32_t pass, int32_t width);
 
 /* Depth in cells (8, 16, 32 or 64) of the 8 x 8 x depth mesh tiles by which
- * particles are binned for the deposit and gather (a tuning knob; results agree up to
- * FP32 summation order).  COLA_ERR_INVALID for other depths, COLA_ERR_UNSUPPORTED_SIZE
- * when depth does not divide nm.  Call cola_workspace_bytes again afterwards.
- * Host-only. */
+ * particles are binned for the deposit and gather (a tuning knob; results are
+ * identical for every depth: the mass deposit sums 64-bit fixed point and a
+ * particle's arithmetic does not depend on its tile; the adjoint's weighted deposits
+ * sum FP32 and agree up to summation order).  COLA_ERR_INVALID for other depths,
+ * COLA_ERR_UNSUPPORTED_SIZE when depth does not divide nm.  Call
+ * cola_workspace_bytes again afterwards.  Host-only. */
 int cola_plan_set_bin_depth(cola_plan plan, int32_t depth);
 
 /* Current tuning: y-pass and x-pass tile widths (0 = built-in default) and bin
