@@ -159,7 +159,7 @@ def test_variant_run_matches_oracle(flags):
     d = x.astype(np.float64) - rx
     d = np.abs(d - cfg.box * np.round(d / cfg.box))
     cell = cfg.box / cfg.nm
-    print(f"[full run 32/64 seed={seed}] max |dx| {err:.3e} Mpc/h = {err / cell:.3e} cells, "
+    print(f"[variant run 32/64 flags={flags}] max |dx| {err:.3e} Mpc/h = {err / cell:.3e} cells, "
           f"99.9th percentile {np.percentile(d, 99.9):.3e} Mpc/h", flush=True)
     assert err <= 1e-3 * cfg.box, err
     assert rel_l2(v, rv.reshape(3, -1).numpy()) < 1e-4
@@ -199,7 +199,7 @@ def test_paper_mesh_ratio_run_matches_oracle(np_side, nm):
     d = x.astype(np.float64) - rx
     d = np.abs(d - cfg.box * np.round(d / cfg.box))
     cell = cfg.box / cfg.nm
-    print(f"[full run 32/64 seed={seed}] max |dx| {err:.3e} Mpc/h = {err / cell:.3e} cells, "
+    print(f"[run {np_side}/{nm} seed=1301] max |dx| {err:.3e} Mpc/h = {err / cell:.3e} cells, "
           f"99.9th percentile {np.percentile(d, 99.9):.3e} Mpc/h", flush=True)
     assert err <= 1e-3 * cfg.box, err
     assert rel_l2(v, rv.reshape(3, -1).numpy()) < 1e-4
