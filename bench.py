@@ -399,7 +399,7 @@ def main() -> int:
     b_alg = b_alg_step(np_side, nm)
 
     out = {
-        "metric": "particle-steps/s, 256^3 COLA PM step",
+        "metric": f"particle-steps/s, {np_side}^3 COLA PM step",
         "value": np_side**3 * cfg.n_steps / (run_ms * 1e-3),
         "unit": "particle-steps/s",
         "n_gpus": 1,
