@@ -13,6 +13,11 @@
   schemes converge to one trajectory at second order; the standard COLA scheme
   keeps linear growth exact with few steps, plain PM does not.
 * v_res(a_0) = 0 after L-(a_0) (eq. Lops).
+* LPT motion is integrated exactly (Section 2 and Appendix A.3: COLA integrates
+  only the residual about the LPT trajectory): with the force replaced by the 2LPT
+  acceleration T^2[D1] s1 + T^2[D2] s2, every step lands on s = D1 s1 + D2 s2 with
+  v_res = 0, and the output velocity is T[D1] s1 + T[D2] s2, for any step count.
+  This pins every first- and second-order term of the kick, the drift and L+-.
 * 2LPT sign convention: the Eulerian density of x = q + D1 s1 + D2 s2 at second
   order reproduces the perturbation-theory kernel
   F2(k1, k2) = 5/7 + mu/2 (k1/k2 + k2/k1) + 2/7 mu^2 (Einstein-de Sitter).
@@ -195,3 +200,34 @@ def test_2lpt_reproduces_second_order_kernel(n1, n2):
         ra = math.sqrt(float(ka @ ka) / float(kb @ kb))
         f2 = 5.0 / 7.0 + 0.5 * mu * (ra + 1.0 / ra) + 2.0 / 7.0 * mu * mu
         assert proj == pytest.approx(f2 * A * B, rel=1e-9, abs=1e-12)
+
+
+@pytest.mark.parametrize("kw", [{"n_steps": 10}, {"n_steps": 3}, {"n_steps": 7, "n_lpt": 1.5},
+                                {"scheme": "standard", "n_steps": 4}, {"log_a_steps": True, "n_steps": 5},
+                                {"u1_drift": True, "n_steps": 6}, {"omega_m": 0.25, "omega_l": 0.75}])
+def test_lpt_motion_is_integrated_exactly(kw, monkeypatch):
+    cfg = cosmo.Config(np_side=8, nm_side=16, **kw)
+    tab = cosmo.step_table(cfg)
+    g = torch.Generator().manual_seed(5)
+    s1 = torch.randn(3, 8, 8, 8, generator=g, dtype=F64)
+    s2 = 0.3 * torch.randn(3, 8, 8, 8, generator=g, dtype=F64)
+
+    def lpt_acceleration(s, a, *args):
+        gr = cosmo.growth([a], cfg)
+        return float(gr["T2D1"][0]) * s1 + float(gr["T2D2"][0]) * s2
+
+    monkeypatch.setattr(cola, "pm_force", lpt_acceleration)
+    x, v_phys, s, states = cola.evolve(s1, s2, cfg, tab, keep_states=True)
+    D1, D2 = tab.grow["D1"], tab.grow["D2"]
+    scale = float(s1.abs().max())
+    for i, st in enumerate(states):
+        assert (st.s - (D1[i] * s1 + D2[i] * s2)).abs().max().item() < 1e-12 * scale, i
+        assert st.v.abs().max().item() < 1e-12 * scale, i
+    n = cfg.n_steps
+    assert (s - (D1[n] * s1 + D2[n] * s2)).abs().max().item() < 1e-12 * scale
+    v_lpt = tab.grow["TD1"][n] * s1 + tab.grow["TD2"][n] * s2
+    assert (v_phys - v_lpt).abs().max().item() < 1e-12 * scale
+    x_lpt = torch.remainder(lpt.lagrangian_grid(8, cfg.box) + D1[n] * s1 + D2[n] * s2, cfg.box)
+    d = x - x_lpt
+    d = d - cfg.box * torch.round(d / cfg.box)
+    assert d.abs().max().item() < 1e-12 * cfg.box
