@@ -112,6 +112,26 @@ def test_drift_factor_at_the_wrong_time_is_caught(monkeypatch):
         pins_cosmo.test_toy_model_is_integrated_exactly(3, -2.5)
 
 
+def test_nyquist_modes_kept_are_caught(monkeypatch):
+    from oracle import fourier
+
+    def without_nyquist_mask(n):
+        nx, ny, nz = fourier.mode_numbers(n)
+        return ~((nx == 0) & (ny == 0) & (nz == 0))
+    monkeypatch.setattr(pm, "kept_modes", without_nyquist_mask)
+    with pytest.raises(AssertionError):
+        pins_pm.test_modes_with_a_nyquist_index_give_no_force(1)
+
+
+def test_force_without_its_time_factor_is_caught(monkeypatch):
+    orig = pm.pm_force
+    wrong = lambda s, a, n_p, n_m, box, om: orig(s, 1.0, n_p, n_m, box, om)    # (3/2) Om instead of (3/2) Om a
+    monkeypatch.setattr(pm, "pm_force", wrong)
+    monkeypatch.setattr(cola, "pm_force", wrong)
+    with pytest.raises(AssertionError):
+        pins_cola.test_zeldovich_plane_wave_converges()
+
+
 def test_unmutated_oracle_passes_the_same_pins():
     # the cases above fail only because of what they plant
     _lpt_motion_pin()
@@ -120,3 +140,5 @@ def test_unmutated_oracle_passes_the_same_pins():
     pins_pm.test_gather_reproduces_linear_fields()
     pins_lpt.test_two_plane_waves_second_order((1, 1, 0), (1, 0, 2))
     pins_cosmo.test_toy_model_is_integrated_exactly(3, -2.5)
+    pins_pm.test_modes_with_a_nyquist_index_give_no_force(1)
+    pins_cola.test_zeldovich_plane_wave_converges()

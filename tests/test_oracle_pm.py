@@ -134,3 +134,28 @@ def test_deposit_and_gather_are_adjoint():
     lhs = (rho * fld[0]).sum().item()
     rhs = (n_m / n_p) ** 3 * pm.cic_gather(fld, s, n_p, box).sum().item()
     assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_modes_with_a_nyquist_index_give_no_force(axis):
+    # reading of the k-space operators: every mode with any |n_i| = N/2 is zeroed.
+    # (-1)^c along one axis times cos(k y') along another is a single mode pair with
+    # a Nyquist index and a non-zero wavenumber elsewhere: its force vanishes, while
+    # keeping it would give a gradient along the other axis.
+    n, box, amp = 16, 50.0, 0.3
+    c = torch.arange(n, dtype=F64)
+    alt = (-1.0) ** c
+    other = (axis + 1) % 3
+    x = (c + 0.5) * box / n
+    k = 2 * math.pi / box * 2
+    shape_a = [1, 1, 1]
+    shape_a[axis] = n
+    shape_o = [1, 1, 1]
+    shape_o[other] = n
+    rho = (1.0 + amp * alt.view(shape_a) * torch.cos(k * x).view(shape_o)).expand(n, n, n).contiguous()
+    g = pm.gradient_fields(rho, box)
+    assert g.abs().max().item() < 1e-14
+    # the same field without the Nyquist factor has the full gradient -amp sin(k x) / k
+    g2 = pm.gradient_fields((1.0 + amp * torch.cos(k * x).view(shape_o)).expand(n, n, n).contiguous(), box)
+    expect = amp / k * torch.sin(k * x).abs().max().item()
+    assert g2[other].abs().max().item() == pytest.approx(expect, rel=1e-12)
