@@ -132,6 +132,29 @@ def test_force_without_its_time_factor_is_caught(monkeypatch):
         pins_cola.test_zeldovich_plane_wave_converges()
 
 
+def test_second_order_growth_normalised_once_is_caught(monkeypatch):
+    # D2 (and its derivatives) divided by D1raw(1) instead of D1raw(1)^2
+    import numpy as np
+    orig = cosmo.growth
+
+    def once(a, cfg):
+        g = dict(orig(a, cfg))
+        raw = float(cosmo._growth_raw(np.array([1.0]), cfg)[0][0])
+        for key in ("D2", "TD2", "T2D2"):
+            g[key] = g[key] * raw
+        return g
+    monkeypatch.setattr(cosmo, "growth", once)
+    with pytest.raises(AssertionError):
+        pins_cosmo.test_d2_matches_standard_fit()
+
+
+def test_time_variable_with_the_wrong_exponent_is_caught(monkeypatch):
+    orig = cosmo.u_of_a
+    monkeypatch.setattr(cosmo, "u_of_a", lambda a, cfg: orig(a, cfg) ** -1)   # a^-n instead of a^n
+    with pytest.raises(AssertionError):
+        pins_cosmo.test_toy_model_is_integrated_exactly(3, -2.5)
+
+
 def test_unmutated_oracle_passes_the_same_pins():
     # the cases above fail only because of what they plant
     _lpt_motion_pin()
@@ -142,3 +165,4 @@ def test_unmutated_oracle_passes_the_same_pins():
     pins_cosmo.test_toy_model_is_integrated_exactly(3, -2.5)
     pins_pm.test_modes_with_a_nyquist_index_give_no_force(1)
     pins_cola.test_zeldovich_plane_wave_converges()
+    pins_cosmo.test_d2_matches_standard_fit()
