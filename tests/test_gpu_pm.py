@@ -72,6 +72,32 @@ def test_unperturbed_lattice_feels_no_force():
         assert host(acc.abs().max()) < 1e-6
 
 
+def test_density_full_size_matches_oracle():
+    """256^3 particles on the 512^3 mesh in the benchmarked launch configuration
+    (bin depth 32), every cell against the oracle's FP64 deposit, same bar as the
+    small cases; the clumped fifth of the particles puts tiles on the crowded list."""
+    np_side, nm, box = 256, 512, 100.0
+    announce("density 256/512")
+    s = _state(np_side, box, 1302, 2.0)
+    with cola.Plan(cola.Config(np=np_side, nm=nm, box=box)) as plan:
+        assert plan.get_tuning()[2] == 32
+        rho = torch.empty(nm**3, dtype=torch.float32, device="cuda")
+        ws = plan.workspace()
+        plan.density(dev(s), rho, ws)
+        got = host(rho).reshape(nm, nm, nm)
+        del ws, rho
+        torch.cuda.empty_cache()
+    ref = pm.cic_deposit(torch.from_numpy(s.astype(np.float64)).reshape(3, np_side, np_side, np_side),
+                         np_side, nm, box).numpy()
+    mass = (nm / np_side) ** 3
+    t_max = np.abs(s).max() * nm / box + 1.0
+    viol = np.abs(got - ref) / (1e-5 * ref + 8 * mass * t_max * 2.0**-22)
+    worst = np.unravel_index(np.argmax(viol), viol.shape)
+    assert viol.max() <= 1.0, (worst, float(got[worst]), float(ref[worst]), int((viol > 1).sum()))
+    assert got.astype(np.float64).sum() == pytest.approx(nm**3, rel=1e-6)
+    assert ref.max() > 1000.0      # the clump: many particles per cell
+
+
 def test_pm_force_full_size_matches_oracle():
     """256^3 particles on the 512^3 mesh, the benchmarked configuration."""
     np_side, nm, box = 256, 512, 100.0
