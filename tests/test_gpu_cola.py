@@ -108,6 +108,37 @@ def test_single_step_matches_oracle(flags):
     assert rel_l2(s, ref.s.reshape(3, -1).numpy()) < 1e-5
 
 
+def test_late_step_full_size_matches_oracle():
+    """One COLA step (force at a_8, kick, drift) at 256^3 particles / 512^3 mesh, the
+    benchmarked configuration, from the clustered state the GPU reached after eight
+    steps: the oracle takes the same FP32 state in FP64.  Bars of the full-size force
+    (the kick's error is the force's) and of the small single steps."""
+    cfg = cola.Config(np=256, nm=512)
+    oc = _ocfg(cfg)
+    table = cosmo.step_table(oc)
+    i = 8
+    announce("late step 256/512")
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        w = torch.empty(256**3, dtype=torch.float32, device="cuda")
+        plan.noise(1302, w)
+        p = cola.Particles.empty(256)
+        plan.init_2lpt(w, p, ws)
+        for k in range(i):
+            plan.step(k, p, ws)
+        before = [host(t) for t in (p.s, p.v, p.s1, p.s2)]
+        plan.step(i, p, ws)
+        s, v = host(p.s), host(p.v)
+        del ws, w, p
+        torch.cuda.empty_cache()
+    st = ocola.State(*(torch.from_numpy(x.reshape(3, 256, 256, 256)).double() for x in before))
+    ref = ocola.step(st, i, table, oc)
+    dv_ref = ref.v.reshape(3, -1).numpy() - before[1].astype(np.float64)
+    assert rel_l2(v.astype(np.float64) - before[1], dv_ref) < 1e-5      # the kick itself
+    assert rel_l2(v, ref.v.reshape(3, -1).numpy()) < 1e-5
+    assert rel_l2(s, ref.s.reshape(3, -1).numpy()) < 1e-5
+
+
 def test_step_index_out_of_range():
     with cola.Plan(cola.Config(np=16, nm=32, n_steps=4)) as plan:
         p = cola.Particles.empty(16)
