@@ -139,6 +139,37 @@ def test_late_step_full_size_matches_oracle():
     assert rel_l2(s, ref.s.reshape(3, -1).numpy()) < 1e-5
 
 
+def test_finish_full_size_matches_oracle():
+    """The closing kick at a_n and L+(a_n) at 256^3 / 512^3 from the state the GPU
+    reached after its ten steps, against the oracle's finish from the same state:
+    x (periodic) and v_phys, bars of the late step."""
+    cfg = cola.Config(np=256, nm=512)
+    oc = _ocfg(cfg)
+    table = cosmo.step_table(oc)
+    announce("finish 256/512")
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        w = torch.empty(256**3, dtype=torch.float32, device="cuda")
+        plan.noise(1302, w)
+        p = cola.Particles.empty(256)
+        plan.init_2lpt(w, p, ws)
+        for k in range(cfg.n_steps):
+            plan.step(k, p, ws)
+        before = [host(t) for t in (p.s, p.v, p.s1, p.s2)]
+        x = torch.empty_like(p.s)
+        v = torch.empty_like(p.s)
+        plan.finish(p, x, v, ws)
+        xg, vg = host(x), host(v)
+        del ws, w, p, x, v
+        torch.cuda.empty_cache()
+    st = ocola.State(*(torch.from_numpy(a.reshape(3, 256, 256, 256)).double() for a in before))
+    rx, rv, _ = ocola.finish(st, table, oc)
+    rx = rx.reshape(3, -1).numpy()
+    assert periodic_max_err(xg, rx, cfg.box) < 1e-4 * cfg.box / cfg.nm
+    assert rel_l2(vg, rv.reshape(3, -1).numpy()) < 1e-5
+    assert xg.min() >= 0.0 and xg.max() < cfg.box
+
+
 def test_step_index_out_of_range():
     with cola.Plan(cola.Config(np=16, nm=32, n_steps=4)) as plan:
         p = cola.Particles.empty(16)
