@@ -120,6 +120,25 @@ def test_pm_force_full_size_matches_oracle():
     assert max_rel_to_rms(got, ref) < 2e-4
 
 
+def test_pm_force_paper_mesh_full_size_matches_oracle():
+    """256^3 particles on the paper's 768^3 mesh (3x per side), against the oracle,
+    bars of the 512^3 case."""
+    np_side, nm, box = 256, 768, 100.0
+    announce("pm_force 256/768")
+    s = _state(np_side, box, 1302, 2.0)
+    with cola.Plan(cola.Config(np=np_side, nm=nm, box=box)) as plan:
+        acc = torch.empty((3, np_side**3), dtype=torch.float32, device="cuda")
+        ws = plan.workspace()
+        plan.pm_force(dev(s), 0.82, acc, ws)
+        got = host(acc)
+        del ws, acc
+        torch.cuda.empty_cache()
+    ref = pm.pm_force(torch.from_numpy(s).double().reshape(3, np_side, np_side, np_side), 0.82, np_side, nm,
+                      box, 0.3).reshape(3, -1).numpy()
+    assert rel_l2(got, ref) < 1e-5
+    assert max_rel_to_rms(got, ref) < 2e-4
+
+
 @pytest.mark.parametrize("np_side,nm", [(32, 64), (128, 256)])
 def test_fft_tile_shapes_agree(np_side, nm):
     """Every valid strided-pass tile width gives the same force bit for bit: the width
