@@ -131,6 +131,25 @@ def _stream(stream=None) -> int:
     return torch.cuda.current_stream().cuda_stream
 
 
+def _need(t, nbytes: int, name: str, dtype_size: int = 4):
+    """Checks a device buffer before its pointer crosses the C-ABI: a CUDA tensor,
+    contiguous, of the element size the entry point reads, at least nbytes long.
+    The library cannot check sizes itself (it receives bare pointers).  None passes
+    through as a null pointer, which every entry point rejects with an error status."""
+    import torch
+    if t is None:
+        return t
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if t.element_size() != dtype_size:
+        raise ValueError(f"{name}: expected {dtype_size}-byte elements, got {t.dtype}")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name}: {t.numel() * t.element_size()} bytes, needs at least {nbytes}")
+    return t
+
+
 @dataclass
 class Config:
     """Mirror of ``cola_config`` with the defaults of the paper's run (Section 2)."""
@@ -170,6 +189,11 @@ class Particles:
 
     def to_c(self) -> ColaParticles:
         return ColaParticles(_ptr(self.s), _ptr(self.v), _ptr(self.s1), _ptr(self.s2))
+
+    def checked(self, np_side: int) -> "Particles":
+        for name in ("s", "v", "s1", "s2"):
+            _need(getattr(self, name), 12 * np_side**3, f"particles.{name}")
+        return self
 
 
 class Plan:
@@ -212,42 +236,70 @@ class Plan:
         return {c: [vals[13 * i + j] for i in range(n)] for j, c in enumerate(STEP_TABLE_COLUMNS)}
 
     # -- device ----------------------------------------------------------------------
+    def _p3(self, bytes_per_particle: int) -> int:
+        return bytes_per_particle * self.cfg.np**3
+
+    def _ws(self, ws):
+        return _need(ws, self.workspace_bytes(), "ws")
+
     def workspace(self, device="cuda"):
         import torch
         return torch.empty(self.workspace_bytes() // 4, dtype=torch.float32, device=device)
 
     def noise(self, seed: int, w, stream=None):
+        _need(w, self._p3(4), "w")
         _check("cola_noise", lib().cola_noise(self._c, seed, _ptr(w), _stream(stream)))
 
     def init_2lpt(self, w, p: Particles, ws, stream=None):
-        cp = p.to_c()
+        _need(w, self._p3(4), "w")
+        self._ws(ws)
+        cp = p.checked(self.cfg.np).to_c()
         _check("cola_init_2lpt", lib().cola_init_2lpt(self._c, _ptr(w), ctypes.byref(cp), _ptr(ws),
                                                       _stream(stream)))
 
     def density(self, s, rho, ws, stream=None):
+        _need(s, self._p3(12), "s")
+        _need(rho, 4 * self.cfg.nm**3, "rho")
+        self._ws(ws)
         _check("cola_density", lib().cola_density(self._c, _ptr(s), _ptr(rho), _ptr(ws), _stream(stream)))
 
     def cross_power(self, s_a, s_b, out, ws, stream=None):
         """cola_cross_power: out (float64, 6 x nm/2 on the device) receives the mode
         count, P_aa, P_bb, P_ab, rho and n_max per shell; s_b may be None."""
+        _need(s_a, self._p3(12), "s_a")
+        if s_b is not None:
+            _need(s_b, self._p3(12), "s_b")
+        _need(out, 8 * 6 * (self.cfg.nm // 2), "out", dtype_size=8)
+        self._ws(ws)
         _check("cola_cross_power", lib().cola_cross_power(self._c, _ptr(s_a), _ptr(s_b),
                                                           _ptr(out), _ptr(ws), _stream(stream)))
 
     def pm_force(self, s, a: float, acc, ws, stream=None):
+        _need(s, self._p3(12), "s")
+        _need(acc, self._p3(12), "acc")
+        self._ws(ws)
         _check("cola_pm_force", lib().cola_pm_force(self._c, _ptr(s), a, _ptr(acc), _ptr(ws),
                                                     _stream(stream)))
 
     def step(self, i: int, p: Particles, ws, stream=None):
-        cp = p.to_c()
+        self._ws(ws)
+        cp = p.checked(self.cfg.np).to_c()
         _check("cola_step", lib().cola_step(self._c, i, ctypes.byref(cp), _ptr(ws), _stream(stream)))
 
     def finish(self, p: Particles, x_out, v_out, ws, stream=None):
-        cp = p.to_c()
+        _need(x_out, self._p3(12), "x_out")
+        _need(v_out, self._p3(12), "v_out")
+        self._ws(ws)
+        cp = p.checked(self.cfg.np).to_c()
         _check("cola_finish", lib().cola_finish(self._c, ctypes.byref(cp), _ptr(x_out), _ptr(v_out),
                                                 _ptr(ws), _stream(stream)))
 
     def run(self, w, p: Particles, x_out, v_out, ws, stream=None):
-        cp = p.to_c()
+        _need(w, self._p3(4), "w")
+        _need(x_out, self._p3(12), "x_out")
+        _need(v_out, self._p3(12), "v_out")
+        self._ws(ws)
+        cp = p.checked(self.cfg.np).to_c()
         _check("cola_run", lib().cola_run(self._c, _ptr(w), ctypes.byref(cp), _ptr(x_out), _ptr(v_out),
                                           _ptr(ws), _stream(stream)))
 

@@ -88,3 +88,15 @@ def test_host_step_table_matches_oracle(kw):
     np.testing.assert_allclose(t["dD2"][:-1], ot.dD2, rtol=1e-8)
     np.testing.assert_allclose(t["a_mid"][:-1], ot.a_mid, rtol=1e-14)
     np.testing.assert_allclose(t["force"], 1.5 * ocfg.omega_m * ot.a, rtol=1e-14)
+
+
+def test_binding_rejects_host_buffers_before_the_call():
+    # the binding checks device, dtype, contiguity and size before a pointer reaches
+    # the library (which receives bare pointers and cannot check sizes)
+    import torch
+    with cola.Plan(cola.Config(np=16, nm=32)) as p:
+        s = torch.zeros(3, 16**3)
+        with pytest.raises(ValueError, match="CUDA"):
+            p.density(s, torch.zeros(32**3), s)
+        with pytest.raises(ValueError, match="CUDA"):
+            p.run(torch.zeros(16**3), cola.Particles(s, s, s, s), s, s, s)

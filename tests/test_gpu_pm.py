@@ -164,3 +164,25 @@ def test_fft_tile_rejects_invalid_width():
             plan.set_fft_tile(0, 16)      # 16 does not divide nm/2 = 8
         with pytest.raises(cola.ColaError):
             plan.set_fft_tile(2, 8)
+
+
+def test_binding_rejects_short_or_mistyped_buffers():
+    with cola.Plan(cola.Config(np=16, nm=32)) as plan:
+        s = torch.zeros(3, 16**3, device="cuda")
+        rho = torch.empty(32**3, device="cuda")
+        ws = plan.workspace()
+        with pytest.raises(ValueError, match="ws"):
+            plan.density(s, rho, ws[: ws.numel() // 2])
+        with pytest.raises(ValueError, match="rho"):
+            plan.density(s, rho[:-1], ws)
+        with pytest.raises(ValueError, match="4-byte"):
+            plan.density(s.double(), rho, ws)
+        with pytest.raises(ValueError, match="contiguous"):
+            plan.pm_force(torch.zeros(16**3, 3, device="cuda").t(), 0.5, s, ws)
+        p = cola.Particles.empty(16)
+        p.s2 = p.s2[:, :-1]
+        with pytest.raises(ValueError, match="particles.s2"):
+            plan.step(0, p, ws)
+        plan.density(s, rho, ws)              # the well-formed call still runs
+        torch.cuda.synchronize()
+        assert abs(float(rho.double().sum()) - 32**3) < 1e-2
