@@ -242,6 +242,13 @@ class Plan:
     def _ws(self, ws):
         return _need(ws, self.workspace_bytes(), "ws")
 
+    def _fft_buffers(self, n: int, inp, out):
+        # n^3 floats in, n * n * (n/2) complex (also n^3 floats) out; sizes other than
+        # np and nm are left to the library, which rejects them
+        if n in (self.cfg.np, self.cfg.nm):
+            _need(inp, 4 * n**3, "in")
+            _need(out, 4 * n**3, "out")
+
     def workspace(self, device="cuda"):
         import torch
         return torch.empty(self.workspace_bytes() // 4, dtype=torch.float32, device=device)
@@ -343,7 +350,12 @@ class Plan:
         return {lib().cola_trace_stage_name(k).decode(): (ms[k], cnt[k]) for k in range(n) if cnt[k]}
 
     def run_checkpointed(self, w, p: Particles, x_out, v_out, ckpt, ws, stream=None):
-        cp = p.to_c()
+        _need(w, self._p3(4), "w")
+        _need(x_out, self._p3(12), "x_out")
+        _need(v_out, self._p3(12), "v_out")
+        _need(ckpt, (self.cfg.n_steps + 1) * self._p3(12), "ckpt")
+        self._ws(ws)
+        cp = p.checked(self.cfg.np).to_c()
         _check("cola_run_checkpointed", lib().cola_run_checkpointed(
             self._c, _ptr(w), ctypes.byref(cp), _ptr(x_out), _ptr(v_out), _ptr(ckpt), _ptr(ws), _stream(stream)))
 
@@ -357,13 +369,20 @@ class Plan:
         return torch.empty(self.adjoint_workspace_bytes() // 4, dtype=torch.float32, device=device)
 
     def run_adjoint(self, w, ckpt, dL_drho, dL_dw, ws, stream=None):
+        _need(w, self._p3(4), "w")
+        _need(ckpt, (self.cfg.n_steps + 1) * self._p3(12), "ckpt")
+        _need(dL_drho, 4 * self.cfg.nm**3, "dL_drho")
+        _need(dL_dw, self._p3(4), "dL_dw")
+        _need(ws, self.adjoint_workspace_bytes(), "ws")
         _check("cola_run_adjoint", lib().cola_run_adjoint(self._c, _ptr(w), _ptr(ckpt), _ptr(dL_drho),
                                                           _ptr(dL_dw), _ptr(ws), _stream(stream)))
 
     def fft_r2c(self, n: int, inp, out, stream=None):
+        self._fft_buffers(n, inp, out)
         _check("cola_fft_r2c", lib().cola_fft_r2c(self._c, n, _ptr(inp), _ptr(out), _stream(stream)))
 
     def fft_c2r(self, n: int, inp, out, stream=None):
+        self._fft_buffers(n, inp, out)
         _check("cola_fft_c2r", lib().cola_fft_c2r(self._c, n, _ptr(inp), _ptr(out), _stream(stream)))
 
 
