@@ -18,9 +18,11 @@ denominator lacks the square root, which the derivation in Appendix B has) and
 n_max(k) = (2/3) rho / sqrt(1 - rho^2), eq. (nmax).  P_x is the shell average of
 Re(delta_a,k delta_b,k^*) with the same weights as P.
 
-Parity unpinned against the paper (Fig. 2 is not recoverable); pinned by a
-single-mode closed form, Parseval's theorem, identities of the cross spectrum and
-the n_max normalisation in the tests.
+Pinned in the tests by a single-mode closed form, Parseval's theorem, the mode
+counts of the shells, identities of the cross spectrum (rho = +-1 for proportional
+fields, bilinearity, symmetry, Cauchy-Schwarz, independent fields uncorrelated) and
+the normalisation of eq. (nmax) that Appendix B fixes (n_max = 2 where 10% of the
+power is residual).  The paper's figures print no values that could be compared.
 """
 from __future__ import annotations
 

@@ -105,3 +105,24 @@ def test_n_max_normalisation():
     assert nm.item() == pytest.approx(2.0, rel=1e-11)
     # per shell, rho lies between sqrt(0.9) (all modes with eps) and 1
     assert bool(((rho >= math.sqrt(0.9) - 1e-12) & (rho <= 1 + 1e-12)).all())
+
+
+def test_parseval_over_the_shells():
+    # a zero-mean field band-limited to |n| < N/4 puts all its power inside shells
+    # 1..N/2, so sum_b P_b n_b = (L^3 / N^6) sum_k |delta_k|^2 = (L^3 / N^3) sum_x delta_x^2
+    n, box = 16, 37.0
+    g = torch.Generator().manual_seed(9)
+    white = torch.randn(n, n, n, generator=g, dtype=F64)
+    dk = torch.fft.rfftn(white)
+    f = torch.fft.fftfreq(n, d=1.0 / n, dtype=F64)
+    kz = torch.fft.rfftfreq(n, d=1.0 / n, dtype=F64)
+    mag = torch.sqrt(f.view(n, 1, 1) ** 2 + f.view(1, n, 1) ** 2 + kz.view(1, 1, -1) ** 2)
+    dk = torch.where((mag < n / 4) & (mag > 0), dk, torch.zeros_like(dk))
+    delta = torch.fft.irfftn(dk, s=(n, n, n))
+    pk, cnt = power.power_from_delta(delta, box)
+    lhs = (pk * cnt).sum().item()
+    rhs = box**3 / n**3 * (delta**2).sum().item()
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    # and the cross estimator of a field with itself gives the same numbers
+    pa, pb, px, cnt2 = power.cross_power_from_delta(delta, delta, box)
+    assert torch.allclose(px, pk, rtol=1e-13) and torch.equal(cnt2, cnt)
