@@ -512,7 +512,10 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
   __syncthreads();
   if (!listed && tile_is_listed(lat, bins, rpre[1])) return;   // block-uniform
   const int total = rpre[kDepRanges];
-  constexpr int U = 2;   // particles per lane per batch, so their dependent loads overlap
+  // particles per lane per batch: a tile's particles plus its neighbours' boundary
+  // classes (about 1.3 per tile thread on average) fit one or two batches, and more
+  // slots per lane only add predicated-off work
+  constexpr int U = 1;
   for (int base = 0; base < total; base += U * D::TT) {   // block-uniform trip count
     float sv[U][3];
     unsigned lg[U];
