@@ -166,3 +166,65 @@ def test_unmutated_oracle_passes_the_same_pins():
     pins_pm.test_modes_with_a_nyquist_index_give_no_force(1)
     pins_cola.test_zeldovich_plane_wave_converges()
     pins_cosmo.test_d2_matches_standard_fit()
+
+
+# --- spectrum normalisation and second-order growth -----------------------------------
+from tests import test_oracle_spectrum as pins_spec   # noqa: E402
+
+
+def _bbks(k, cfg, gamma, c=(2.34, 3.89, 16.1, 5.46, 6.71)):
+    import numpy as np
+    q = np.asarray(k, dtype=np.float64) / gamma
+    x = c[0] * q
+    with np.errstate(divide="ignore", invalid="ignore"):
+        lead = np.where(x > 1e-8, np.log1p(x) / np.where(x > 0, x, 1.0), 1.0 - 0.5 * x)
+    return lead * (1.0 + c[1] * q + (c[2] * q) ** 2 + (c[3] * q) ** 3 + (c[4] * q) ** 4) ** -0.25
+
+
+def test_shape_parameter_with_h_squared_is_caught(monkeypatch):
+    monkeypatch.setattr(cosmo, "bbks_transfer", lambda k, cfg: _bbks(k, cfg, cfg.omega_m * cfg.h**2))
+    with pytest.raises(AssertionError):
+        pins_spec.test_bbks_depends_on_k_over_omega_m_h(0.3, 0.7, 0.3, 0.5)
+    with pytest.raises(AssertionError):
+        pins_spec.test_power_amplitude_matches_independent_value()
+
+
+@pytest.mark.parametrize("coeffs", [(2.34, 3.98, 16.1, 5.46, 6.71), (2.34, 3.89, 16.1, 5.64, 6.71),
+                                    (2.43, 3.89, 16.1, 5.46, 6.71)])
+def test_mistyped_transfer_coefficient_is_caught(coeffs, monkeypatch):
+    monkeypatch.setattr(cosmo, "bbks_transfer", lambda k, cfg: _bbks(k, cfg, cfg.omega_m * cfg.h, coeffs))
+    with pytest.raises(AssertionError):
+        pins_spec.test_power_amplitude_matches_independent_value()
+
+
+def test_tophat_without_its_factor_three_is_caught(monkeypatch):
+    orig = cosmo.tophat_window
+    monkeypatch.setattr(cosmo, "tophat_window", lambda x: orig(x) / 3.0)
+    with pytest.raises(AssertionError):
+        with pytest.MonkeyPatch.context() as inner:
+            pins_spec.test_tophat_variance_of_white_noise(inner)
+    with pytest.raises(AssertionError):
+        pins_spec.test_power_amplitude_matches_independent_value()
+
+
+def test_second_order_growth_off_by_1e4_is_caught(monkeypatch):
+    orig = cosmo.growth
+
+    def off(a, cfg):
+        g = dict(orig(a, cfg))
+        g["D2"] = g["D2"] * (1.0 + 1e-4)
+        return g
+    monkeypatch.setattr(cosmo, "growth", off)
+    with pytest.raises(AssertionError):
+        pins_spec.test_d2_matches_variation_of_parameters(0.3, 0.7)
+    with pytest.raises(AssertionError):
+        pins_spec.test_step_table_matches_independent_values()
+
+
+def test_unmutated_spectrum_pins_pass():
+    with pytest.MonkeyPatch.context() as inner:
+        pins_spec.test_tophat_variance_of_white_noise(inner)
+    pins_spec.test_bbks_depends_on_k_over_omega_m_h(0.3, 0.7, 0.3, 0.5)
+    pins_spec.test_power_amplitude_matches_independent_value()
+    pins_spec.test_d2_matches_variation_of_parameters(0.3, 0.7)
+    pins_spec.test_step_table_matches_independent_values()
