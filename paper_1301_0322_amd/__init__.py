@@ -330,7 +330,7 @@ class Plan:
         _check("cola_tuning_workspace_bytes", lib().cola_tuning_workspace_bytes(self._c, ctypes.byref(need)))
         if ws is None or ws.numel() * 4 < need.value:
             ws = torch.empty(need.value // 4 + 1, dtype=torch.float32, device=p.s.device)
-        cp = p.to_c()
+        cp = p.checked(self.cfg.np).to_c()
         used = ctypes.c_int32()
         path = cache_path.encode() if cache_path else None
         _check("cola_autotune", lib().cola_autotune(self._c, ctypes.byref(cp), _ptr(ws), ws.numel() * 4,
@@ -394,7 +394,18 @@ class Ensemble:
     def __init__(self, plans, noises, device="cuda"):
         import torch
         self.plans = list(plans)
-        self.noises = [w.contiguous() for w in noises]
+        noises = list(noises)
+        if not self.plans or len(noises) != len(self.plans):
+            raise ValueError(f"{len(self.plans)} plans and {len(noises)} noise arrays: need one per member")
+        # the graph bakes in bare pointers, so every member's noise is checked before
+        # anything is allocated or captured (a short buffer would be read past on
+        # every replay)
+        self._c = _VP()
+        self.noises = []
+        for k, (pl, w) in enumerate(zip(self.plans, noises)):
+            if isinstance(w, torch.Tensor):
+                w = w.contiguous()
+            self.noises.append(_need(w, 4 * pl.cfg.np**3, f"noises[{k}]"))
         self.particles = [Particles.empty(pl.cfg.np, device) for pl in self.plans]
         self.ws = [pl.workspace(device) for pl in self.plans]
         self.x = [torch.empty((3, pl.cfg.np**3), dtype=torch.float32, device=device) for pl in self.plans]
@@ -402,7 +413,6 @@ class Ensemble:
         n = len(self.plans)
         arr = lambda vals: (_VP * n)(*vals)
         parts = (ColaParticles * n)(*[p.to_c() for p in self.particles])
-        self._c = _VP()
         _check("cola_ensemble_create", lib().cola_ensemble_create(
             n, arr([pl._c for pl in self.plans]), arr([_ptr(w) for w in self.noises]), parts,
             arr([_ptr(x) for x in self.x]), arr([_ptr(v) for v in self.v]), arr([_ptr(w) for w in self.ws]),

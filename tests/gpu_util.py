@@ -14,16 +14,23 @@ def host(t) -> np.ndarray:
     return t.detach().to("cpu").numpy()
 
 
+def _as_f64(a) -> np.ndarray:
+    """float64 view of real data; complex data as (real, imaginary) pairs, so both
+    parts take part in every error norm."""
+    a = np.asarray(a)
+    if np.iscomplexobj(a):
+        return np.stack([a.real, a.imag]).astype(np.float64)
+    return a.astype(np.float64)
+
+
 def rel_l2(got, ref) -> float:
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    got, ref = _as_f64(got), _as_f64(ref)
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
 
 
 def max_rel_to_rms(got, ref) -> float:
-    """max |got - ref| / rms(ref)."""
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
+    """max |got - ref| / rms(ref) (complex: over real and imaginary parts)."""
+    got, ref = _as_f64(got), _as_f64(ref)
     return float(np.abs(got - ref).max() / max(np.sqrt((ref * ref).mean()), 1e-300))
 
 

@@ -100,3 +100,20 @@ def test_binding_rejects_host_buffers_before_the_call():
             p.density(s, torch.zeros(32**3), s)
         with pytest.raises(ValueError, match="CUDA"):
             p.run(torch.zeros(16**3), cola.Particles(s, s, s, s), s, s, s)
+
+
+def test_ensemble_checks_every_noise_before_the_call():
+    # the ensemble graph bakes in bare pointers: every member's noise is checked (a
+    # CUDA tensor of at least np^3 floats) before anything is allocated or captured
+    import torch
+    plans = [cola.Plan(cola.Config(np=16, nm=32)), cola.Plan(cola.Config(np=24, nm=48))]
+    try:
+        with pytest.raises(ValueError, match="noises\\[0\\].*CUDA"):
+            cola.Ensemble(plans, [torch.zeros(16**3), torch.zeros(24**3)])
+        with pytest.raises(ValueError, match="one per member"):
+            cola.Ensemble(plans, [torch.zeros(16**3)])
+        with pytest.raises(ValueError, match="one per member"):
+            cola.Ensemble([], [])
+    finally:
+        for p in plans:
+            p.close()
