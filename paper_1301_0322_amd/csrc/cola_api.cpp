@@ -168,7 +168,9 @@ Lattice lattice(cola_plan p) {
   l.np = p->cfg.np;
   l.nm = p->cfg.nm;
   l.ratio = p->cfg.nm / p->cfg.np;
-  l.inv_dx = (float)(p->cfg.nm / p->cfg.box);
+  const double inv_dx = p->cfg.nm / p->cfg.box;
+  l.inv_dx = (float)inv_dx;
+  l.inv_dx_lo = (float)(inv_dx - (double)l.inv_dx);
   l.npart = cube(p->cfg.np);
   set_lattice_divisor(l);
   return l;
@@ -222,10 +224,9 @@ struct BinPlan {
 // Bins the particles at q + s by Eulerian tile (unless prebinned) and deposits
 // their CIC density (mean 1) into rho; the bins stay valid for a gather from the
 // same s.
-int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t st, BinPlan bp = {}) {
+int deposit_with(cola_plan p, const float* s, float* rho, const BinBuffers& bb, hipStream_t st, BinPlan bp) {
   const Lattice lat = lattice(p);
   const Bins& b = p->bins;
-  const BinBuffers bb = bin_buffers(p, ws, bp.parity);
   const double ratio = (double)lat.ratio;
   if (!bp.prebinned) COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, s, bb, st); }));
   COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, bp.bin_next, st); }));
@@ -233,6 +234,10 @@ int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t
   COLA_HIP(traced(p, kStDeposit, st,
                   [&] { return launch_deposit(lat, b, s, bb, rho, (float)(ratio * ratio * ratio), st); }));
   return COLA_OK;
+}
+
+int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t st, BinPlan bp = {}) {
+  return deposit_with(p, s, rho, bin_buffers(p, ws, bp.parity), st, bp);
 }
 
 // Poisson solve on the density in ws mesh 0: g_d = (3/2) Om a irfft(i k_d delta_k / k^2),
@@ -324,13 +329,15 @@ int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_
   k.beta = (float)row.beta;
   k.dd1 = plain ? 0.0f : (float)row.dd1;
   k.dd2 = plain ? 0.0f : (float)row.dd2;
-  GatherArgs g = gather_args(p, ws);
-  g.s = q->s;
-  g.v = q->v;
-  g.s1 = q->s1;
-  g.s2 = q->s2;
+  // The caller's Lagrangian-order arrays are read through the tile lists (each tile's
+  // records prefetched while its force tile is staged) and s, v are written back in
+  // place; the arithmetic is the tile-sorted cola_run gather's, so both paths agree
+  // bit for bit.
+  const GatherArgs g = gather_args(p, ws);
+  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
   return hip_status(traced(p, kStGatherKickDrift, st, [&] {
-    return launch_gather(lattice(p), p->bins, bin_buffers(p, ws, bp.parity), kGatherKickDrift, bp.bin_next, g, k, st);
+    return launch_gather_sorted(lattice(p), p->bins, lagr, lagr, bin_buffers(p, ws, bp.parity), kGatherKickDriftLag,
+                                g, k, st);
   }));
 }
 
@@ -354,9 +361,15 @@ int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out
   g.s2 = q->s2;
   g.out_a = x_out;
   g.out_b = v_out;
-  return hip_status(traced(p, kStFinish, st, [&] {
-    return launch_gather(lattice(p), p->bins, bin_buffers(p, ws, bp.parity), kGatherFinish, false, g, k, st);
+  // as the closing step of cola_run: the kick in tile order into a workspace copy,
+  // then back to Lagrangian order with L+ and the positions
+  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
+  const SortedState out = sorted_state(p, ws, 0);
+  const Lattice lat = lattice(p);
+  COLA_HIP(traced(p, kStFinish, st, [&] {
+    return launch_gather_sorted(lat, p->bins, lagr, out, bin_buffers(p, ws, bp.parity), kGatherFinish, g, k, st);
   }));
+  return hip_status(traced(p, kStUnsort, st, [&] { return launch_unsort(lat, out, g, k, st); }));
 }
 
 // ---------------------------------------------------------------------------------
@@ -756,7 +769,7 @@ int cola_pm_force(cola_plan p, const float* s, double a, float* acc, void* ws_, 
   g.out_a = acc;
   return hip_status(
       traced(p, kStGatherForce, st, [&] {
-        return launch_gather(lattice(p), p->bins, bin_buffers(p, ws), kGatherForce, false, g, KickArgs{}, st);
+        return launch_gather_force(lattice(p), p->bins, bin_buffers(p, ws), g, st);
       }));
 }
 

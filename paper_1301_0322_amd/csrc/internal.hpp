@@ -92,7 +92,8 @@ struct Lattice {
   int np;           // particles per side
   int nm;           // mesh cells per side
   int ratio;        // nm / np
-  float inv_dx;     // nm / L
+  float inv_dx;     // nm / L rounded to float
+  float inv_dx_lo;  // nm / L - inv_dx (the rounding remainder, as a float)
   long npart;       // np^3
   // x / np for x < 2^31 as (x * np_magic) >> (31 + np_shift): np_shift = ceil(log2 np),
   // np_magic = floor(2^(31 + np_shift) / np) + 1 (Granlund and Montgomery 1994, the
@@ -170,10 +171,13 @@ struct KickArgs {
   float td1, td2;              // T[D1](a_n), T[D2](a_n) for L+ (finish)
   float box;
 };
+// Modes of launch_gather_sorted (the force-only gather is launch_gather_force).
 enum GatherMode : int {
-  kGatherForce = 0,     // acc_d = F_d
-  kGatherKickDrift = 1, // v += alpha (F - t2d1 s1 - t2d2 s2); s += beta v + dd1 s1 + dd2 s2
-  kGatherFinish = 2,    // kick, then x = (q + s) mod L, v_out = v + td1 s1 + td2 s2
+  kGatherKickDrift = 1,     // v += alpha (F - t2d1 s1 - t2d2 s2); s += beta v + dd1 s1 + dd2 s2, written
+                            // packed in this step's tile order and binned for the next step
+  kGatherFinish = 2,        // the kick only, written packed for launch_unsort (x, L+)
+  kGatherKickDriftLag = 3,  // kick and drift of the caller's Lagrangian-order arrays in place
+                            // (src = dst = SoA s, v, s1, s2; no binning)
 };
 struct GatherArgs {
   const float* g0;
@@ -183,13 +187,12 @@ struct GatherArgs {
   float* v;
   const float* s1;
   const float* s2;
-  float* out_a;     // kGatherForce: acc; kGatherFinish: x
-  float* out_b;     // kGatherFinish: v_phys
+  float* out_a;     // force gather: acc; launch_unsort: x
+  float* out_b;     // launch_unsort: v_phys
 };
-// bin_next (kGatherKickDrift only): also count the drifted particles into
-// bb.count_next and write their (key, rank) to bb.key_rank for the next step.
-hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
-                         hipStream_t st);
+// Force gather (cola_pm_force): a.out_a[d n + p] = F_d of particle p of the SoA
+// displacements a.s, through the tile lists of bb.
+hipError_t launch_gather_force(Lattice lat, Bins b, BinBuffers bb, GatherArgs a, hipStream_t st);
 
 // Particle state ordered by tile (slot j), with each particle's Lagrangian index.
 // lag == nullptr: the caller's SoA arrays s, v, s1, s2 ([3][n], slot = Lagrangian

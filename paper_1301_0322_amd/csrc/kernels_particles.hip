@@ -85,9 +85,14 @@ __device__ __forceinline__ void tile_add(unsigned long long* p, float x) {
 __device__ __forceinline__ float tile_value(float v) { return v; }
 __device__ __forceinline__ float tile_value(unsigned long long v) { return (float)(long long)v * (1.f / kFixScale); }
 
-// Base cell (wrapped) and CIC fraction along one axis.
-__device__ __forceinline__ int base_cell(int lag, int ratio, float s, float inv_dx, int nm, float& frac) {
-  const float t = fmaf(s, inv_dx, -0.5f);
+// Base cell (wrapped) and CIC fraction along one axis.  t = s nm / L - 1/2 with nm / L
+// carried as the float pair inv_dx + inv_dx_lo: a single float nm / L is off by up to
+// 2^-24 relative, which would shift every particle by that fraction of its displacement
+// in cells -- a bias, not noise, for particles that moved far -- so only t's own final
+// rounding remains.
+__device__ __forceinline__ int base_cell(int lag, int ratio, float s, float inv_dx, float inv_dx_lo, int nm,
+                                         float& frac) {
+  const float t = fmaf(s, inv_dx, fmaf(s, inv_dx_lo, -0.5f));
   const float ft = floorf(t);
   frac = t - ft;
   const int c = ratio * lag + (int)ft;
@@ -116,7 +121,8 @@ __device__ __forceinline__ Stencil stencil_of(const Lattice& lat, unsigned p, co
   lag_index(lat, p, li);
   Stencil st;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) st.c[d] = base_cell(li[d], lat.ratio, sv[d], lat.inv_dx, lat.nm, st.f[d]);
+  for (int d = 0; d < 3; ++d)
+    st.c[d] = base_cell(li[d], lat.ratio, sv[d], lat.inv_dx, lat.inv_dx_lo, lat.nm, st.f[d]);
   return st;
 }
 
@@ -586,15 +592,14 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
 }
 
 // ---------------------------------------------------------------------------------
-// Gather + kick (+ drift | + finish), tile by tile.  With BIN_NEXT the drifted
-// particles are also counted into next step's tiles (count_next, key_rank_next).
+// Force gather, tile by tile: the PM force at every particle of the caller's
+// Lagrangian-order displacements (cola_pm_force).  The kick and drift gathers are
+// k_gather_sorted's.
 // ---------------------------------------------------------------------------------
-template <int TZ, int MODE, bool BIN_NEXT>
+template <int TZ>
 __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_tiles(Lattice lat, Bins bins, const int* __restrict__ idx,
                                                                const int* __restrict__ offset,
-                                                               const int* __restrict__ heavy, GatherArgs g,
-                                                               KickArgs k, int2* __restrict__ key_rank_next,
-                                                               int* __restrict__ count_next) {
+                                                               const int* __restrict__ heavy, GatherArgs g) {
   using D = TileDims<TZ>;
   __shared__ float tile[3 * D::EXT];
   TileGeom t;
@@ -607,61 +612,26 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_tiles(Lattice lat, 
   stage_fields<TZ, 3>(t, lat.nm, gf, tile);
   __syncthreads();
   const long n = lat.npart;
-  for (int base = beg; base < end; base += D::TT) {   // block-uniform trip count
-    const int i = base + threadIdx.x;
-    const unsigned p = (unsigned)idx[i < end ? i : base];
+  for (int i = beg + threadIdx.x; i < end; i += D::TT) {
+    const unsigned p = (unsigned)idx[i];
     float sv[3], fr[3];
     int lc[3];
-    const bool act = local_stencil<TZ>(lat, t, g.s, p, p, sv, lc, fr) && i < end;
+    if (!local_stencil<TZ>(lat, t, g.s, p, p, sv, lc, fr)) continue;   // cannot happen
     float f[3] = {0.f, 0.f, 0.f};
-    if (act) {
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const float wab = (a ? fr[0] : 1.f - fr[0]) * (b ? fr[1] : 1.f - fr[1]);
-          const float w0 = wab * (1.f - fr[2]), w1 = wab * fr[2];
-          const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
+      for (int b = 0; b < 2; ++b) {
+        const float wab = (a ? fr[0] : 1.f - fr[0]) * (b ? fr[1] : 1.f - fr[1]);
+        const float w0 = wab * (1.f - fr[2]), w1 = wab * fr[2];
+        const int o = ((lc[0] + a) * D::EY + lc[1] + b) * D::EZ + lc[2];
 #pragma unroll
-          for (int d = 0; d < 3; ++d)
-            f[d] += w0 * corner_value<TZ>(tile + d * D::EXT, gf[d], o, T_, lc[0] + a, lc[1] + b, lc[2], lat.nm) +
-                    w1 * corner_value<TZ>(tile + d * D::EXT, gf[d], o + 1, T_, lc[0] + a, lc[1] + b, lc[2] + 1, lat.nm);
-        }
-    }
-    float snew[3] = {sv[0], sv[1], sv[2]};
-    if (act) {
-      if constexpr (MODE == kGatherForce) {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) g.out_a[d * n + p] = f[d];
-      } else {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const float a1 = g.s1[d * n + p];
-          const float a2 = g.s2[d * n + p];
-          float v = g.v[d * n + p];
-          v += k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
-          g.v[d * n + p] = v;
-          if constexpr (MODE == kGatherKickDrift) {
-            snew[d] = sv[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
-            g.s[d * n + p] = snew[d];
-          } else {
-            g.out_b[d * n + p] = v + k.td1 * a1 + k.td2 * a2;
-            int li[3];
-            lag_index(lat, p, li);
-            float x = (float)li[d] * (k.box / (float)lat.np) + sv[d];
-            x = x - k.box * floorf(x / k.box);
-            if (x >= k.box) x -= k.box;
-            g.out_a[d * n + p] = x;
-          }
-        }
+        for (int d = 0; d < 3; ++d)
+          f[d] += w0 * corner_value<TZ>(tile + d * D::EXT, gf[d], o, T_, lc[0] + a, lc[1] + b, lc[2], lat.nm) +
+                  w1 * corner_value<TZ>(tile + d * D::EXT, gf[d], o + 1, T_, lc[0] + a, lc[1] + b, lc[2] + 1, lat.nm);
       }
-    }
-    if constexpr (BIN_NEXT) {
-      int bin = 0;
-      if (act) bin = key_of<TZ>(bins, stencil_of(lat, p, snew).c);
-      const int rank = wave_rank(act, bin, count_next);
-      if (act) key_rank_next[p] = make_int2(bin, rank);
-    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) g.out_a[d * n + p] = f[d];
   }
 }
 
@@ -839,11 +809,16 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
       for (int d = 0; d < 3; ++d) {
         const float a1 = r.s1[d], a2 = r.s2[d];
         const float v = r.v[d] + k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
-        if constexpr (MODE == kGatherKickDrift) {
+        if constexpr (MODE == kGatherKickDrift || MODE == kGatherKickDriftLag)
           snew[d] = r.s[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
-          vf[d] = v;
-        } else {
-          vf[d] = v;
+        vf[d] = v;
+      }
+      if constexpr (MODE == kGatherKickDriftLag) {
+        // the caller's arrays, in place: each particle is read and written by one lane
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          dst.s[d * n + r.lag] = snew[d];
+          dst.v[d * n + r.lag] = vf[d];
         }
       }
       if constexpr (MODE == kGatherKickDrift) {
@@ -1036,28 +1011,9 @@ hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, fl
   return hipGetLastError();
 }
 
-template <int TZ>
-static void gather_tz(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
-                      hipStream_t st) {
-  const dim3 grid(tile_blocks(b)), block(TileDims<TZ>::TT);
-  if (mode == kGatherForce)
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherForce, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy, a, k,
-                       bb.key_rank, bb.count_next);
-  else if (mode == kGatherKickDrift && bin_next)
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, true>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy, a,
-                       k, bb.key_rank, bb.count_next);
-  else if (mode == kGatherKickDrift)
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherKickDrift, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy,
-                       a, k, bb.key_rank, bb.count_next);
-  else
-    hipLaunchKernelGGL((k_gather_tiles<TZ, kGatherFinish, false>), grid, block, 0, st, lat, b, bb.idx, bb.offset, bb.heavy, a,
-                       k, bb.key_rank, bb.count_next);
-}
-
-hipError_t launch_gather(Lattice lat, Bins b, BinBuffers bb, int mode, bool bin_next, GatherArgs a, KickArgs k,
-                         hipStream_t st) {
-  if (mode != kGatherForce && mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
-  COLA_TZ_DISPATCH(b.tz, gather_tz<TZ>(lat, b, bb, mode, bin_next, a, k, st));
+hipError_t launch_gather_force(Lattice lat, Bins b, BinBuffers bb, GatherArgs a, hipStream_t st) {
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL(k_gather_tiles<TZ>, dim3(tile_blocks(b)), dim3(TileDims<TZ>::TT), 0, st,
+                                            lat, b, bb.idx, bb.offset, bb.heavy, a));
   return hipGetLastError();
 }
 
@@ -1068,6 +1024,9 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
   if (mode == kGatherKickDrift)
     hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, src, dst, bb.idx,
                        bb.offset, bb.heavy, a, k, bb.key_rank, bb.count_next);
+  else if (mode == kGatherKickDriftLag)
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDriftLag>), grid, block, 0, st, lat, b, src, dst, bb.idx,
+                       bb.offset, bb.heavy, a, k, bb.key_rank, bb.count_next);
   else
     hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherFinish>), grid, block, 0, st, lat, b, src, dst, bb.idx, bb.offset, bb.heavy,
                        a, k, bb.key_rank, bb.count_next);
@@ -1075,9 +1034,14 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
 
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st) {
-  if (mode != kGatherKickDrift && mode != kGatherFinish) return hipErrorInvalidValue;
-  // dst is always packed: 12 n floats from dst.s, 16-byte aligned, and n ints of lag
-  if (!dst.s || !dst.lag || reinterpret_cast<uintptr_t>(dst.s) % 16 != 0) return hipErrorInvalidValue;
+  if (mode != kGatherKickDrift && mode != kGatherFinish && mode != kGatherKickDriftLag) return hipErrorInvalidValue;
+  if (mode == kGatherKickDriftLag) {
+    // dst is the caller's SoA arrays (s, v) in Lagrangian order, and so is src
+    if (!dst.s || !dst.v || dst.lag || src.lag) return hipErrorInvalidValue;
+  } else if (!dst.s || !dst.lag || reinterpret_cast<uintptr_t>(dst.s) % 16 != 0) {
+    // dst is packed: 12 n floats from dst.s, 16-byte aligned, and n ints of lag
+    return hipErrorInvalidValue;
+  }
   if (src.lag && reinterpret_cast<uintptr_t>(src.s) % 16 != 0) return hipErrorInvalidValue;
   COLA_TZ_DISPATCH(b.tz, gather_sorted_tz<TZ>(lat, b, src, dst, bb, mode, a, k, st));
   return hipGetLastError();
