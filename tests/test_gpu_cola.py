@@ -170,6 +170,59 @@ def test_finish_full_size_matches_oracle():
     assert xg.min() >= 0.0 and xg.max() < cfg.box
 
 
+@pytest.mark.timeout(900)
+def test_target_run_full_size_matches_oracle():
+    """The benchmarked workload end to end against the FP64 oracle: 256^3 particles on the
+    512^3 mesh, 2LPT at z = 9 and 10 COLA steps to z = 0 (Section 2; eq. (ALCtimestep)),
+    from the Philox white noise of seed 1302 (the oracle's generator, rounded to float32,
+    so both sides get the same array; the library's own cola_noise agrees with it to
+    5e-6).  Every particle's position within 1e-3 of the box (per component, periodic),
+    the final P(k) within 1e-4 over shells 1..256, v_phys within 1e-4 relative L2 (the
+    bars of the small runs)."""
+    cfg = cola.Config(np=256, nm=512)
+    oc = _ocfg(cfg)
+    w = philox.white_noise(1302, 256**3).astype(np.float32)
+    announce("target run 256/512 on the GPU")
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        p = cola.Particles.empty(256)
+        x = torch.empty((3, 256**3), dtype=torch.float32, device="cuda")
+        v = torch.empty_like(x)
+        plan.run(dev(w), p, x, v, ws)
+        xg, vg = host(x), host(v)
+        del ws, p, x, v
+        torch.cuda.empty_cache()
+    table = cosmo.step_table(oc)
+    rs1, rs2 = lpt.lpt_from_noise(w.astype(np.float64), oc)
+    st = ocola.initial_state(rs1, rs2, table)
+    del rs1, rs2
+    for i in range(oc.n_steps):
+        st = ocola.step(st, i, table, oc)
+        announce(f"target run 256/512: oracle step {i} done")
+    rx, rv, _ = ocola.finish(st, table, oc)
+    del st
+    rx = rx.reshape(3, -1).numpy()
+    rv = rv.reshape(3, -1).numpy()
+    d = xg.astype(np.float64) - rx
+    d = np.abs(d - cfg.box * np.round(d / cfg.box))
+    err = float(d.max())
+    cell = cfg.box / cfg.nm
+    print(f"[target run 256/512 seed=1302] max |dx| {err:.3e} Mpc/h = {err / cell:.3e} cells "
+          f"= {err / cfg.box:.3e} L, 99.9th percentile {np.percentile(d, 99.9):.3e} Mpc/h", flush=True)
+    del d
+    assert err <= 1e-3 * cfg.box, err
+    ev = rel_l2(vg, rv)
+    pk_gpu, _ = power.power_of_positions(torch.from_numpy(xg.astype(np.float64)), cfg.nm, cfg.box)
+    pk_orc, _ = power.power_of_positions(torch.from_numpy(rx), cfg.nm, cfg.box)
+    rel = (pk_gpu / pk_orc - 1.0).abs()
+    print(f"[target run 256/512 seed=1302] v_phys rel L2 {ev:.3e}; P(k) max rel {rel.max().item():.3e} "
+          f"over {rel.numel()} shells", flush=True)
+    assert rel.numel() == cfg.nm // 2
+    assert rel.max().item() <= 1e-4
+    assert ev < 1e-4
+    assert xg.min() >= 0.0 and xg.max() < cfg.box
+
+
 def test_step_index_out_of_range():
     with cola.Plan(cola.Config(np=16, nm=32, n_steps=4)) as plan:
         p = cola.Particles.empty(16)

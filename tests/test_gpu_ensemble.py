@@ -10,8 +10,11 @@ import pytest
 import torch
 
 import paper_1301_0322_amd as cola
+from oracle import cola as ocola
+from oracle import cosmology as cosmo
+from oracle import philox, power
 from paper_1301_0322_amd import inputs
-from tests.gpu_util import announce, dev, host, rel_l2
+from tests.gpu_util import announce, dev, host, periodic_max_err, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -67,3 +70,65 @@ def test_autotune_picks_valid_shapes_and_caches(tmp_path):
         assert plan2.autotune(p, None, cache) is True
         assert plan2.get_tuning() == (y, x, tz)
     assert "np=64 nm=128" in open(cache).read()
+
+
+# One member of each ensemble size of the benchmarked ensemble (16 members each of
+# 64^3/128^3, 96^3/192^3 and 128^3/256^3 in 100 Mpc/h boxes, seeds 1..48) with a second
+# member of each size beside it in the graph.
+C3_MEMBERS = [(64, 128, 1), (64, 128, 2), (96, 192, 17), (96, 192, 18), (128, 256, 33), (128, 256, 34)]
+
+
+@pytest.mark.timeout(900)
+def test_ensemble_members_match_oracle():
+    """Graph replays against the FP64 oracle: every member of the graph above, on its
+    own white noise (the oracle's Philox stream of its seed, rounded to float32, for
+    both sides), at the bars of the single runs -- positions within 1e-3 of the box,
+    the final P(k) within 1e-4 over shells 1..nm/2, v_phys within 1e-4 relative L2 --
+    on the first and the second replay of the graph."""
+    plans = [cola.Plan(cola.Config(np=n, nm=m)) for n, m, _ in C3_MEMBERS]
+    noise = [philox.white_noise(seed, n**3).astype(np.float32) for n, _, seed in C3_MEMBERS]
+    announce("ensemble of three sizes: create")
+    ens = cola.Ensemble(plans, [dev(w) for w in noise])
+    outs = []
+    for rep in range(2):
+        for t in ens.x + ens.v:
+            t.fill_(float("nan"))
+        announce(f"ensemble of three sizes: launch {rep}")
+        ens.launch()
+        torch.cuda.synchronize()
+        outs.append([(host(ens.x[k]), host(ens.v[k])) for k in range(len(plans))])
+    ens.close()
+    for pl in plans:
+        pl.close()
+    for k, (n, m, seed) in enumerate(C3_MEMBERS):
+        oc = cosmo.Config(np_side=n, nm_side=m)
+        announce(f"ensemble member {k} ({n}/{m}, seed {seed}): oracle")
+        rx, rv, _ = ocola.run(noise[k].astype(np.float64), oc)
+        rx = rx.reshape(3, -1).numpy()
+        rv = rv.reshape(3, -1).numpy()
+        pk_orc, _ = power.power_of_positions(torch.from_numpy(rx), m, oc.box)
+        for rep, out in enumerate(outs):
+            x, v = out[k]
+            err = periodic_max_err(x, rx, oc.box)
+            pk_gpu, _ = power.power_of_positions(torch.from_numpy(x.astype(np.float64)), m, oc.box)
+            rel = (pk_gpu / pk_orc - 1.0).abs().max().item()
+            ev = rel_l2(v, rv)
+            print(f"[ensemble member {n}/{m} seed {seed} replay {rep}] max |dx| {err:.3e} Mpc/h, "
+                  f"P(k) max rel {rel:.3e}, v_phys rel L2 {ev:.3e}", flush=True)
+            assert err <= 1e-3 * oc.box, (k, rep, err)
+            assert rel <= 1e-4, (k, rep, rel)
+            assert ev < 1e-4, (k, rep, ev)
+
+
+def test_ensemble_rejects_a_short_noise():
+    # a 64^3 noise handed to a 128^3 member, or a float64 one: rejected before capture
+    plans = [cola.Plan(cola.Config(np=32, nm=64)), cola.Plan(cola.Config(np=128, nm=256))]
+    try:
+        ok = torch.zeros(32**3, dtype=torch.float32, device="cuda")
+        with pytest.raises(ValueError, match="noises\\[1\\].*needs at least"):
+            cola.Ensemble(plans, [ok, torch.zeros(64**3, dtype=torch.float32, device="cuda")])
+        with pytest.raises(ValueError, match="noises\\[1\\].*4-byte"):
+            cola.Ensemble(plans, [ok, torch.zeros(128**3, dtype=torch.float64, device="cuda")])
+    finally:
+        for p in plans:
+            p.close()

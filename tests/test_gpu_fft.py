@@ -84,3 +84,89 @@ def test_fft_rejects_foreign_size():
         buf = torch.empty(128**3, dtype=torch.float32, device="cuda")
         with pytest.raises(cola.ColaError):
             plan.fft_r2c(128, buf, buf)
+
+
+# ------------------------------------------------------------------------------------
+# Every size, 768 and 1024 included, against an analytic spectrum: a sum of a few
+# cosines f(j) = sum_m a_m cos(2 pi k_m.j / n + phi_m) has the DFT
+# F(k) = (n^3 a_m / 2) e^{+-i phi_m} at k = +-k_m and zero elsewhere.  No host FFT is
+# needed, so the largest meshes are compared element by element.  Modes have
+# 1 <= kz <= n/2 - 1 (only +k_m lies in the stored half spectrum) except one kz = 0
+# mode, whose conjugate partner (-kx, -ky, 0) is stored too.  Inputs are built on the
+# device in float64 from exact integer phases, then rounded to float32.
+# ------------------------------------------------------------------------------------
+def _modes(n):
+    h = n // 2
+    return [((1, 2, 3), 1.0, 0.3), ((n - 5, 7, h - 1), 0.5, -1.1), ((h - 3, n - 1, 1), 0.25, 2.0),
+            ((3, n - 4, 0), 0.75, 0.7)]
+
+
+def _cosine_field(n):
+    dev_ = torch.device("cuda")
+    ax = torch.arange(n, device=dev_, dtype=torch.int64)
+    f = torch.zeros((n, n, n), dtype=torch.float64, device=dev_)
+    for (kx, ky, kz), a, ph in _modes(n):
+        m = (kx * ax.view(n, 1, 1) + ky * ax.view(1, n, 1) + kz * ax.view(1, 1, n)) % n
+        f += a * torch.cos(m.double() * (2 * math.pi / n) + ph)
+        del m
+    return f
+
+
+def _expected_coefficients(n):
+    """{(kx, ky, kz): complex} over the stored half spectrum (kz < n/2)."""
+    out = {}
+    for (kx, ky, kz), a, ph in _modes(n):
+        c = 0.5 * a * n**3
+        out[(kx, ky, kz)] = out.get((kx, ky, kz), 0) + c * complex(math.cos(ph), math.sin(ph))
+        if kz == 0:
+            key = ((-kx) % n, (-ky) % n, 0)
+            out[key] = out.get(key, 0) + c * complex(math.cos(ph), -math.sin(ph))
+    return out
+
+
+ALL_SIZES = sorted({n for pair in PLANS for n in pair})
+
+
+@pytest.mark.parametrize("n", ALL_SIZES)
+def test_r2c_matches_analytic_spectrum(n):
+    with cola.Plan(cola.Config(np=n, nm=n)) as plan:
+        announce(f"fft_r2c analytic n={n}")
+        x = _cosine_field(n).float().reshape(-1)
+        out = torch.empty(n**3, dtype=torch.float32, device="cuda")
+        plan.fft_r2c(n, x, out)
+        del x
+        spec = out.view(n, n, n // 2, 2)
+        total = (spec.double() ** 2).sum().item()
+        exp = _expected_coefficients(n)
+        err2, ref2, at_modes = 0.0, 0.0, 0.0
+        for (kx, ky, kz), c in exp.items():
+            re, im = (float(v) for v in spec[kx, ky, kz].double().cpu())
+            at_modes += re * re + im * im
+            err2 += (re - c.real) ** 2 + (im - c.imag) ** 2
+            ref2 += abs(c) ** 2
+        leak2 = max(total - at_modes, 0.0)
+        err = math.sqrt((err2 + leak2) / ref2)
+        print(f"[r2c analytic n={n}] rel L2 {err:.3e} (leakage {math.sqrt(leak2 / ref2):.3e})", flush=True)
+        del out, spec
+        torch.cuda.empty_cache()
+    assert err < 2e-6, err
+
+
+@pytest.mark.parametrize("n", ALL_SIZES)
+def test_c2r_matches_analytic_field(n):
+    with cola.Plan(cola.Config(np=n, nm=n)) as plan:
+        announce(f"fft_c2r analytic n={n}")
+        half = torch.zeros((n, n, n // 2, 2), dtype=torch.float32, device="cuda")
+        for (kx, ky, kz), c in _expected_coefficients(n).items():
+            half[kx, ky, kz, 0] = c.real
+            half[kx, ky, kz, 1] = c.imag
+        out = torch.empty(n**3, dtype=torch.float32, device="cuda")
+        plan.fft_c2r(n, half.view(-1), out)
+        del half
+        ref = _cosine_field(n)
+        got = out.view(n, n, n).double()
+        err = (torch.linalg.vector_norm(got - ref) / torch.linalg.vector_norm(ref)).item()
+        print(f"[c2r analytic n={n}] rel L2 {err:.3e}", flush=True)
+        del out, ref, got
+        torch.cuda.empty_cache()
+    assert err < 2e-6, err

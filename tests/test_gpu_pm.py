@@ -43,6 +43,8 @@ def test_density_matches_oracle(np_side, nm, box, rms):
     t_max = np.abs(s).max() * nm / box + 1.0
     viol = np.abs(got - ref) / (1e-5 * ref + 8 * mass * t_max * 2.0**-22)
     worst = np.unravel_index(np.argmax(viol), viol.shape)
+    print(f"[density np={np_side} nm={nm} rms={rms}] max |diff| {np.abs(got - ref).max():.3e} "
+          f"(mean density 1), bar use {viol.max():.3f}", flush=True)
     assert viol.max() <= 1.0, (worst, float(got[worst]), float(ref[worst]), int((viol > 1).sum()))
     assert got.sum() == pytest.approx(nm**3, rel=1e-5)
 
@@ -186,3 +188,68 @@ def test_binding_rejects_short_or_mistyped_buffers():
         plan.density(s, rho, ws)              # the well-formed call still runs
         torch.cuda.synchronize()
         assert abs(float(rho.double().sum()) - 32**3) < 1e-2
+
+
+@pytest.mark.timeout(900)
+def test_pm_force_large_mesh_matches_oracle():
+    """The 1024^3 mesh of the large box (400 Mpc/h): 256^3 particles with Gaussian
+    displacements of 8 Mpc/h rms (20 cells, the scale of the large box's z = 0
+    displacements), force of eq. (eom) against the oracle's FP64 force at every
+    particle.  Bars of the 512^3 case; the FFT error grows only as log n.
+
+    No clump here: the clumped inputs pull a fifth of the particles across the box,
+    to mesh coordinates |t| ~ 700 cells, where the FP32 rounding of t (|t| 2^-24 per
+    rounding) moves the CIC weights by ~1e-4 of a cell and the force by about 1e-5
+    relative; that is the precision of FP32 displacements, not of the FFT, and the
+    density test below keeps the clump."""
+    np_side, nm, box = 256, 1024, 400.0
+    announce("pm_force 256/1024")
+    s = inputs.displacements(np_side, box, 1303, rms=8.0, clump_frac=0.0)
+    with cola.Plan(cola.Config(np=np_side, nm=nm, box=box)) as plan:
+        acc = torch.empty((3, np_side**3), dtype=torch.float32, device="cuda")
+        ws = plan.workspace()
+        sd = dev(s)
+        plan.pm_force(sd, 0.64, acc, ws)
+        got = host(acc)
+        del ws, sd, acc
+        torch.cuda.empty_cache()
+    announce("pm_force 256/1024: oracle")
+    ref = pm.pm_force(torch.from_numpy(s).double().reshape(3, np_side, np_side, np_side), 0.64, np_side, nm,
+                      box, 0.3).reshape(3, -1).numpy()
+    e2, em = rel_l2(got, ref), max_rel_to_rms(got, ref)
+    print(f"[pm_force 256/1024] rel L2 {e2:.3e}, max / rms {em:.3e}, "
+          f"max |t| {np.abs(s).max() * nm / box:.0f} cells", flush=True)
+    assert e2 < 1e-5
+    assert em < 2e-4
+
+
+@pytest.mark.timeout(900)
+def test_density_large_box_matches_oracle():
+    """The large-box workload's particle and mesh counts (512^3 particles on the 1024^3
+    mesh, 400 Mpc/h; a fifth of the particles pulled into one clump): every one of the
+    2^30 cells against the oracle's FP64 deposit, bar of the small cases.  This is also
+    the parity check of the particle-index decode at np = 512."""
+    np_side, nm, box = 512, 1024, 400.0
+    announce("density 512/1024")
+    s = _state(np_side, box, 1303, 4.0)
+    with cola.Plan(cola.Config(np=np_side, nm=nm, box=box)) as plan:
+        rho = torch.empty(nm**3, dtype=torch.float32, device="cuda")
+        ws = plan.workspace()
+        sd = dev(s)
+        plan.density(sd, rho, ws)
+        got = host(rho).reshape(nm, nm, nm)
+        del ws, sd, rho
+        torch.cuda.empty_cache()
+    announce("density 512/1024: oracle")
+    ref = pm.cic_deposit(torch.from_numpy(s).double().reshape(3, np_side, np_side, np_side), np_side, nm,
+                         box).numpy()
+    mass = (nm / np_side) ** 3
+    t_max = np.abs(s).max() * nm / box + 1.0
+    diff = np.abs(got - ref)
+    viol = diff / (1e-5 * ref + 8 * mass * t_max * 2.0**-22)
+    worst = np.unravel_index(np.argmax(viol), viol.shape)
+    print(f"[density 512/1024] max |diff| {diff.max():.3e} (mean density 1), "
+          f"max |diff| / rho {float((diff / ref)[ref > 1e-3].max()):.3e} where rho > 1e-3, "
+          f"bar use {viol.max():.3f}", flush=True)
+    assert viol.max() <= 1.0, (worst, float(got[worst]), float(ref[worst]), int((viol > 1).sum()))
+    assert got.astype(np.float64).sum() == pytest.approx(nm**3, rel=1e-6)
