@@ -142,6 +142,79 @@ def read_profile_avg(stage: str, workload: str, tz: int):
     return None
 
 
+# ------------------------------------------------------------------------------------
+# rocprofv3 summaries (the text files under profiles/): --rocprof-trace DIR reads the
+# kernel_trace.csv files of a `rocprofv3 --kernel-trace --output-format csv -d DIR` run,
+# --rocprof-pmc DIR the counter_collection.csv files of a `--pmc` run.
+# ------------------------------------------------------------------------------------
+def _short_kernel_name(name: str) -> str:
+    name = name.strip().strip('"')
+    if name.startswith("void "):
+        name = name[5:]
+    depth, out = 0, []
+    for ch in name:            # drop the argument list, keep template arguments
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            break
+        out.append(ch)
+    return "".join(out).replace("cola::", "").strip()
+
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    rows = []
+    for root, _, files in os.walk(directory):
+        for f in sorted(files):
+            if f.endswith(suffix):
+                with open(os.path.join(root, f), newline="") as fh:
+                    rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    return rows
+
+
+def rocprof_trace_summary(directory: str, per_dispatch=("k_deposit_tiles", "k_gather_sorted")) -> str:
+    """Kernel table (calls, mean and total duration, share) of a kernel trace, and the
+    duration of every dispatch, in launch order, of the kernels named in per_dispatch."""
+    rows = _csv_rows(directory, "kernel_trace.csv")
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    stats, seq = {}, {}
+    for r in rows:
+        name = _short_kernel_name(r["Kernel_Name"])
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3   # us
+        c, t = stats.get(name, (0, 0.0))
+        stats[name] = (c + 1, t + dt)
+        if any(name.startswith(k) for k in per_dispatch):
+            seq.setdefault(name, []).append(dt)
+    total = sum(t for _, t in stats.values())
+    lines = [f"source_digest: {csrc_digest()}", "",
+             f"{'kernel':<52} {'calls':>6} {'avg_us':>10} {'total_ms':>10} {'pct':>6}"]
+    for name, (c, t) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"{name:<52} {c:>6} {t / c:>10.1f} {t * 1e-3:>10.3f} {100 * t / total:>6.2f}")
+    for name, v in seq.items():
+        lines.append("")
+        lines.append(f"per-dispatch us, {name} (launch order): " + " ".join(f"{x:.1f}" for x in v))
+    return "\n".join(lines)
+
+
+def rocprof_pmc_summary(directory: str) -> str:
+    """Mean value per dispatch of every collected counter, per kernel."""
+    rows = _csv_rows(directory, "counter_collection.csv")
+    acc = {}
+    for r in rows:
+        name = _short_kernel_name(r["Kernel_Name"])
+        key = (name, r["Counter_Name"])
+        c, t = acc.get(key, (0, 0.0))
+        acc[key] = (c + 1, t + float(r["Counter_Value"]))
+    lines = [f"source_digest: {csrc_digest()}", "", f"{'kernel':<52} {'counter':<28} {'dispatches':>10} {'mean':>16}"]
+    for (name, ctr), (c, t) in sorted(acc.items()):
+        lines.append(f"{name:<52} {ctr:<28} {c:>10} {t / c:>16.1f}")
+    return "\n".join(lines)
+
+
 def cpu_baseline(np_side: int, nm: int, box: float, seed: int) -> dict:
     """The FP64 oracle on one COLA step of the same workload (ICs untimed)."""
     import numpy as np
@@ -165,6 +238,7 @@ def cpu_baseline(np_side: int, nm: int, box: float, seed: int) -> dict:
     assert np.isfinite(st.s.sum().item())
     return {
         "value": steps * np_side**3 / dt, "unit": "particle-steps/s", "cores": torch.get_num_threads(),
+        "threads": torch.get_num_threads(), "affinity_cores": len(os.sched_getaffinity(0)),
         "kind": "oracle",
         "sample": f"the first {steps} COLA steps (PM force, kick, drift) of the {np_side}^3/{nm}^3 workload "
                   f"in FP64 torch-CPU, after oracle 2LPT ICs from the same Philox seed (ICs untimed); "
@@ -186,6 +260,20 @@ def timed(fn, stream, reps=1):
     b.record(stream)
     b.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def copy_bandwidth(stream, nbytes: int = 1 << 30) -> dict:
+    """Measured device-to-device copy rate (read + write bytes per second) of a 1 GiB
+    buffer, the practical streaming ceiling beside the 8 TB/s peak."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = timed(lambda: dst.copy_(src), stream, reps=5)
+    del src, dst
+    return {"bytes_moved": 2 * nbytes, "ms": ms, "gb_per_s": 2 * nbytes / (ms * 1e-3) / 1e9,
+            "frac_of_peak": 2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
 def bench_ensemble(stream) -> dict:
@@ -312,7 +400,15 @@ def main() -> int:
     ap.add_argument("--no-analysis", action="store_true", help="skip timing cola_cross_power")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy 256 MiB device to device once (a known-size kernel for HBM byte counters)")
+    ap.add_argument("--rocprof-trace", metavar="DIR", help="print the summary of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--rocprof-pmc", metavar="DIR", help="print the summary of a rocprofv3 --pmc run and exit")
     args = ap.parse_args()
+    if args.rocprof_trace:
+        print(rocprof_trace_summary(args.rocprof_trace))
+        return 0
+    if args.rocprof_pmc:
+        print(rocprof_pmc_summary(args.rocprof_pmc))
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU form of this method is described, not built)", file=sys.stderr)
@@ -399,7 +495,9 @@ def main() -> int:
     b_alg = b_alg_step(np_side, nm)
 
     out = {
-        "metric": f"particle-steps/s, {np_side}^3 COLA PM step",
+        "metric": f"particle-steps/s, {np_side}^3 COLA PM step (value: whole cola_run per bench step = 2LPT ICs "
+                  f"+ {cfg.n_steps} PM steps + closing kick; the PM step alone under pm_step), % HBM roofline; "
+                  f"adjoint/forward time",
         "value": np_side**3 * cfg.n_steps / (run_ms * 1e-3),
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -425,7 +523,14 @@ def main() -> int:
                     / (HBM_PEAK_GBS * 1e9),
                     "timed": f"each COLA step inside cola_run, HIP events around the step only, "
                              f"mean of {steps_rec[1]} steps",
-                    "cola_step_call_ms": api_step_ms},
+                    "cola_step_call": {
+                        "ms": api_step_ms, "particle_steps_per_s": np_side**3 / (api_step_ms * 1e-3),
+                        "hbm_frac": b_alg / (api_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                        "hbm_frac_three_chains": b_alg_three_chains(np_side, nm) / (api_step_ms * 1e-3)
+                        / (HBM_PEAK_GBS * 1e9),
+                        "timed": "the public cola_step call on the caller's Lagrangian-order arrays (bins from "
+                                 "scratch each call), HIP events around each call, median over steps 1.."
+                                 f"{cfg.n_steps - 1} after cola_init_2lpt"}},
         "stages_per_run": per_run,
         "tuning": tuning,
     }
@@ -460,6 +565,7 @@ def main() -> int:
         torch.cuda.empty_cache()
         out["c2"] = bench_paper_mesh(args.steps, "c2")
         torch.cuda.empty_cache()
+    out["copy_bandwidth"] = copy_bandwidth(stream)
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
