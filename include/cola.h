@@ -54,6 +54,7 @@ extern "C" {
 #define COLA_ERR_RANGE (-3)            /* step index out of range */
 #define COLA_ERR_HIP (-4)              /* a HIP runtime call failed */
 #define COLA_ERR_DEVICE (-5)           /* plan used on a different device than its tables */
+#define COLA_ERR_WORKSPACE (-6)        /* the call needs more scratch than the library's static array */
 
 /* Variant flags (eq. KDKALC is the default). */
 #define COLA_FLAG_KDK_STD 0x1u      /* standard COLA discretisation, eq. (KDKALCstd) */
@@ -133,6 +134,25 @@ int cola_init_2lpt(cola_plan plan, const float *w, const cola_particles *p, void
 
 /* Mean-1 CIC density of the particles at q + s: rho (device, nm^3 floats). */
 int cola_density(cola_plan plan, const float *s, float *rho, void *ws, void *stream);
+
+/* cola_density without a caller workspace and without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  The particle binning buffers (8-byte key and rank plus a
+ * 4-byte slot per particle, three int arrays of one entry per tile key, the scan sums
+ * and the crowded-tile list) live in a file-scope device array of 256 MiB, one per GPU,
+ * held from the first call on that GPU until the process ends: that covers every
+ * configuration up to np = 256 (e.g. 256^3 particles on the 512^3 mesh).
+ * s: device [3][np^3] displacements; rho: device nm^3 floats, the mean-1 CIC density
+ * (identical to cola_density's).  Enqueues kernels on stream only: no hipMalloc, no
+ * plan-table upload, no event creation.
+ * Calls on one GPU share that GPU's array, so calls that overlap in time on one GPU
+ * (different streams or threads) race and must be ordered by the caller; the array
+ * keeps the last call's contents, which no call relies on (counters are cleared by
+ * kernels every call).
+ * Errors: COLA_ERR_INVALID for a null plan, s or rho, or a plan with tracing on;
+ * COLA_ERR_WORKSPACE when the plan's binning buffers exceed 256 MiB (checked before
+ * any device call); COLA_ERR_HIP if the array's device address cannot be obtained. */
+int cola_density_noalloc(cola_plan plan, const float *s, float *rho, void *stream);
 
 /* Density statistics of Section 3.1: the shell-averaged power spectra of the mean-1
  * CIC densities of two particle sets at q + s_a and q + s_b (device, [3][np^3]

@@ -50,6 +50,7 @@ _PROTOS = {
     "cola_noise": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
     "cola_init_2lpt": (ctypes.c_int, [_VP, _VP, ctypes.POINTER(ColaParticles), _VP, _VP]),
     "cola_density": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP]),
+    "cola_density_noalloc": (ctypes.c_int, [_VP, _VP, _VP, _VP]),
     "cola_cross_power": (ctypes.c_int, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "cola_pm_force": (ctypes.c_int, [_VP, _VP, ctypes.c_double, _VP, _VP, _VP]),
     "cola_step": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.POINTER(ColaParticles), _VP, _VP]),
@@ -269,6 +270,14 @@ class Plan:
         _need(rho, 4 * self.cfg.nm**3, "rho")
         self._ws(ws)
         _check("cola_density", lib().cola_density(self._c, _ptr(s), _ptr(rho), _ptr(ws), _stream(stream)))
+
+    def density_noalloc(self, s, rho, stream=None):
+        """cola_density without a workspace: the binning buffers live in the library's
+        static per-GPU scratch (256 MiB); raises ColaError (status -6) beyond it.  Calls
+        that overlap in time on one GPU race."""
+        _need(s, self._p3(12), "s")
+        _need(rho, 4 * self.cfg.nm**3, "rho")
+        _check("cola_density_noalloc", lib().cola_density_noalloc(self._c, _ptr(s), _ptr(rho), _stream(stream)))
 
     def cross_power(self, s_a, s_b, out, ws, stream=None):
         """cola_cross_power: out (float64, 6 x nm/2 on the device) receives the mode

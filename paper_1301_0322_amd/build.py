@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libcola_mi355x.so")
-SOURCES = ["kernels_fft.hip", "kernels_particles.hip", "cola_api.cpp", "cosmology.cpp"]
+SOURCES = ["kernels_fft.hip", "kernels_particles.hip", "cola_api.cpp", "cosmology.cpp", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -560,6 +560,20 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
 
 }  // namespace
 
+namespace cola {
+
+int record_hip(hipError_t e) { return hip_status(e); }
+
+size_t plan_bin_bytes(cola_plan_s* p) { return bin_workspace_bytes(cube(p->cfg.np), p->bins); }
+
+int density_with_bins(cola_plan_s* p, const float* s, float* rho, void* bin_base, hipStream_t st) {
+  if (p->trace) return COLA_ERR_INVALID;   // trace events are created on demand
+  const BinBuffers bb = carve_bins(bin_base, cube(p->cfg.np), p->bins);
+  return deposit_with(p, s, rho, bb, st, BinPlan{});
+}
+
+}  // namespace cola
+
 extern "C" {
 
 int cola_plan_create(const cola_config* cfg, cola_plan* out) {
@@ -1180,6 +1194,8 @@ const char* cola_strerror(int status) {
       return "HIP runtime error (see cola_last_hip_error)";
     case COLA_ERR_DEVICE:
       return "plan tables live on another device";
+    case COLA_ERR_WORKSPACE:
+      return "the configuration needs more than the library's static scratch (256 MiB of binning buffers)";
     default:
       return "unknown status";
   }

@@ -5,6 +5,8 @@
 #include <cstddef>
 #include <cstdint>
 
+struct cola_plan_s;
+
 namespace cola {
 
 constexpr int kMaxFields = 9;
@@ -248,5 +250,16 @@ hipError_t launch_xmul_adj(int n, int mode, FieldPtrs in, int nin, float2* out, 
                            hipStream_t st);
 
 hipError_t launch_noise(uint64_t seed, float* w, long count, hipStream_t st);
+
+// Entry points of the allocation-free density (defined with the plan in cola_api.cpp).
+// record_hip: COLA status of a HIP error, kept for cola_last_hip_error().
+// plan_bin_bytes: bytes of the binning buffers of the plan's particle and tile counts.
+// density_with_bins: the mean-1 CIC density of particles at q + s into rho, with the
+// binning buffers carved from bin_base (plan_bin_bytes(p) bytes, 256-byte aligned);
+// enqueues kernels only (no allocation, no plan-table upload); COLA_ERR_INVALID when
+// the plan traces (its events are created on demand).
+int record_hip(hipError_t e);
+size_t plan_bin_bytes(cola_plan_s* p);
+int density_with_bins(cola_plan_s* p, const float* s, float* rho, void* bin_base, hipStream_t st);
 
 }  // namespace cola

@@ -117,3 +117,15 @@ def test_ensemble_checks_every_noise_before_the_call():
     finally:
         for p in plans:
             p.close()
+
+
+def test_density_noalloc_rejects_sizes_beyond_its_scratch():
+    # 512^3 particles need 1.6 GB of binning buffers, more than the 256 MiB static
+    # scratch: rejected with COLA_ERR_WORKSPACE before any device call (the pointers
+    # are never touched)
+    with cola.Plan(cola.Config(np=512, nm=1024, box=400.0)) as p:
+        assert cola.lib().cola_density_noalloc(p._c, 1, 1, None) == -6
+        assert "static scratch" in cola.lib().cola_strerror(-6).decode()
+    with cola.Plan(cola.Config(np=16, nm=32)) as p:
+        assert cola.lib().cola_density_noalloc(p._c, None, 1, None) == -1
+        assert cola.lib().cola_density_noalloc(None, 1, 1, None) == -1
