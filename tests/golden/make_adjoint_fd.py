@@ -15,7 +15,11 @@ the sweep's table is written to the header).  The loss is piecewise smooth (clou
 cell weights have kinks), so the difference quotient has a truncation error that
 shrinks with eps until FP64 round-off of L / eps takes over.
 
-Usage: python tests/golden/make_adjoint_fd.py [--sweep] [--eps EPS] [--threads N]
+With --autograd the script also writes, for the same directions, the oracle's exact
+directional derivatives g.d (g = dL/dw by FP64 autograd through the oracle), read back
+beside the stored differences: the two FP64 routes agree to the differences' accuracy.
+
+Usage: python tests/golden/make_adjoint_fd.py [--sweep] [--eps EPS] [--autograd] [--threads N]
 """
 from __future__ import annotations
 
@@ -71,6 +75,50 @@ def loss(w64, cfg, amp, rho_t) -> float:
     return float(((final_density(w64, cfg, amp) - rho_t) ** 2).sum())
 
 
+def oracle_gradient(cfg: cosmo.Config, amp: float, rho_t: torch.Tensor) -> np.ndarray:
+    """dL/dw at the white noise of seed SEED_W by FP64 autograd through the oracle."""
+    w = torch.from_numpy(inputs.white_noise(NP, SEED_W).astype(np.float64)).requires_grad_(True)
+    (g,) = torch.autograd.grad(((final_density(w, cfg, amp) - rho_t) ** 2).sum(), w)
+    return g.numpy()
+
+
+def read_golden(path: str = OUT):
+    """(eps, loss, fd per direction, autograd g.d per direction or None)."""
+    eps, loss0, fd, ag = None, None, [], []
+    with open(path) as fh:
+        for line in fh:
+            f = line.split()
+            if f[:2] == ["#", "eps"] and len(f) == 3:
+                eps = float(f[2])
+            elif f and f[0] == "loss":
+                loss0 = float(f[1])
+            elif f and f[0] == "dir":
+                fd.append(float(f[2]))
+            elif f and f[0] == "autograd":
+                ag.append(float(f[2]))
+    return eps, loss0, np.array(fd), (np.array(ag) if ag else None)
+
+
+def write_golden(eps: float, l0: float, fd, ag=None, path: str = OUT):
+    with open(path, "w") as fh:
+        fh.write("# FP64 central differences of L(w) = sum (rho(w) - rho_t)^2, written by\n")
+        fh.write(f"#   python tests/golden/make_adjoint_fd.py --eps {eps:g}\n")
+        if ag is not None:
+            fh.write("# and the oracle's autograd directional derivatives g.d, added by\n")
+            fh.write("#   python tests/golden/make_adjoint_fd.py --autograd\n")
+        fh.write(f"# np {NP} nm {NM} box {BOX} seed_w {SEED_W} seed_t {SEED_T} dir_seed {DIR_SEED} n_dir {N_DIR}\n")
+        fh.write(f"# eps {eps!r}\n")
+        fh.write("# eps sweep (--sweep):\n")
+        for line in SWEEP.splitlines():
+            fh.write(f"#   {line}\n")
+        fh.write(f"loss {float(l0)!r}\n")
+        for k, v in enumerate(fd):
+            fh.write(f"dir {k} {float(v)!r}\n")
+        if ag is not None:
+            for k, v in enumerate(ag):
+                fh.write(f"autograd {k} {float(v)!r}\n")
+
+
 def directions() -> np.ndarray:
     rng = np.random.default_rng(DIR_SEED)
     d = rng.standard_normal((N_DIR, NP**3))
@@ -82,6 +130,7 @@ def main() -> int:
     ap.add_argument("--sweep", action="store_true")
     ap.add_argument("--eps", type=float, default=None)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--autograd", action="store_true")
     args = ap.parse_args()
     if args.threads:
         torch.set_num_threads(args.threads)
@@ -93,6 +142,16 @@ def main() -> int:
     l0 = loss(w0, cfg, amp, rho_t)
     print(f"L(w0) = {l0!r} ({time.perf_counter() - t0:.1f} s)", flush=True)
     dirs = directions()
+    if args.autograd:
+        eps, l_file, fd, _ = read_golden()
+        if abs(l_file / l0 - 1.0) > 1e-12:
+            raise SystemExit("the stored loss is not this workload's")
+        g = oracle_gradient(cfg, amp, rho_t)
+        ag = dirs @ g
+        write_golden(eps, l_file, fd, ag)
+        print("autograd g.d:", ag[:4], "... max |fd - g.d| / rms(fd):",
+              float(np.abs(fd - ag).max() / np.sqrt(np.mean(fd**2))))
+        return 0
     if args.sweep:
         for k in range(2):
             d = torch.from_numpy(dirs[k])
@@ -108,17 +167,7 @@ def main() -> int:
         fd = (loss(w0 + args.eps * d, cfg, amp, rho_t) - loss(w0 - args.eps * d, cfg, amp, rho_t)) / (2 * args.eps)
         rows.append(fd)
         print(f"dir {k} fd {fd!r} ({time.perf_counter() - t0:.0f} s)", flush=True)
-    with open(OUT, "w") as fh:
-        fh.write("# FP64 central differences of L(w) = sum (rho(w) - rho_t)^2, written by\n")
-        fh.write(f"#   python tests/golden/make_adjoint_fd.py --eps {args.eps:g}\n")
-        fh.write(f"# np {NP} nm {NM} box {BOX} seed_w {SEED_W} seed_t {SEED_T} dir_seed {DIR_SEED} n_dir {N_DIR}\n")
-        fh.write(f"# eps {args.eps!r}\n")
-        fh.write("# eps sweep (--sweep):\n")
-        for line in SWEEP.splitlines():
-            fh.write(f"#   {line}\n")
-        fh.write(f"loss {l0!r}\n")
-        for k, fd in enumerate(rows):
-            fh.write(f"dir {k} {fd!r}\n")
+    write_golden(args.eps, l0, rows)
     print("wrote", OUT)
     return 0
 

@@ -37,3 +37,16 @@ def test_autograd_gradient_matches_central_differences():
         with torch.no_grad():
             fd = (_loss(w0 + eps * d, cfg, target) - _loss(w0 - eps * d, cfg, target)) / (2 * eps)
         assert (grad @ d).item() == pytest.approx(fd.item(), rel=1e-6)
+
+
+def test_stored_finite_differences_match_the_oracle_gradient():
+    # tests/golden/adjoint_fd_128_256.txt holds, for 32 random directions of the
+    # 128^3/256^3 differentiable workload, FP64 central differences of the oracle's loss
+    # and the oracle's FP64 autograd directional derivatives (both written by
+    # tests/golden/make_adjoint_fd.py): two independent routes to the same derivative,
+    # which agree to the differences' accuracy (the eps sweep in the file's header)
+    from tests.golden import make_adjoint_fd as fdg
+    eps, loss, fd, ag = fdg.read_golden()
+    assert eps == 1e-6 and len(fd) == fdg.N_DIR and ag is not None and len(ag) == fdg.N_DIR
+    rms = np.sqrt(np.mean(fd**2))
+    assert np.abs(fd - ag).max() <= 1e-4 * rms
