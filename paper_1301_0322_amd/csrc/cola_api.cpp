@@ -214,30 +214,23 @@ SortedState sorted_state(cola_plan p, float* ws, int which) {
   return ss;
 }
 
-// How a PM force evaluation obtains its particle bins.
-struct BinPlan {
-  bool prebinned = false;   // counts and ranks already produced by the previous gather
-  bool bin_next = false;    // this step's gather bins the drifted particles
-  int parity = 0;
-};
-
-// Bins the particles at q + s by Eulerian tile (unless prebinned) and deposits
-// their CIC density (mean 1) into rho; the bins stay valid for a gather from the
-// same s.
-int deposit_with(cola_plan p, const float* s, float* rho, const BinBuffers& bb, hipStream_t st, BinPlan bp) {
+// Bins the particles at q + s (caller's Lagrangian-order arrays) by Eulerian tile and
+// deposits their CIC density (mean 1) into rho; the bins stay valid for a gather from
+// the same s.
+int deposit_with(cola_plan p, const float* s, float* rho, const BinBuffers& bb, hipStream_t st) {
   const Lattice lat = lattice(p);
   const Bins& b = p->bins;
   const double ratio = (double)lat.ratio;
-  if (!bp.prebinned) COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, s, bb, st); }));
-  COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, bp.bin_next, st); }));
+  COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, s, bb, st); }));
+  COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, false, st); }));
   COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
   COLA_HIP(traced(p, kStDeposit, st,
                   [&] { return launch_deposit(lat, b, s, bb, rho, (float)(ratio * ratio * ratio), st); }));
   return COLA_OK;
 }
 
-int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t st, BinPlan bp = {}) {
-  return deposit_with(p, s, rho, bin_buffers(p, ws, bp.parity), st, bp);
+int deposit_into(cola_plan p, const float* s, float* rho, float* ws, hipStream_t st) {
+  return deposit_with(p, s, rho, bin_buffers(p, ws), st);
 }
 
 // Poisson solve on the density in ws mesh 0: g_d = (3/2) Om a irfft(i k_d delta_k / k^2),
@@ -292,9 +285,9 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   return COLA_OK;
 }
 
-// The force mesh of particles at q + s (binning them first unless prebinned).
-int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st, BinPlan bp = {}) {
-  COLA_TRY(deposit_into(p, s, ws, ws, st, bp));
+// The force mesh of particles at q + s (binned first).
+int pm_mesh(cola_plan p, const float* s, double a, float* ws, hipStream_t st) {
+  COLA_TRY(deposit_into(p, s, ws, ws, st));
   return fft_force(p, a, ws, st);
 }
 
@@ -317,10 +310,34 @@ int check_particles(const cola_particles* q) {
   return COLA_OK;
 }
 
-// One COLA step: PM force at a_i, merged kick, drift (eq. KDKALC).
-int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st, BinPlan bp) {
+// The caller's Lagrangian-order particles binned by tile and packed into the tile-sorted
+// workspace copy pk (slot = list position; the caller's arrays are read in order), the
+// CIC density deposited from pk and the force meshes solved: the state a cola_run step
+// starts from, so the public calls run the same deposit and gather kernels.
+int packed_mesh(cola_plan p, const cola_particles* q, double a, float* ws, hipStream_t st, SortedState& pk) {
+  const Lattice lat = lattice(p);
+  const Bins& b = p->bins;
+  const BinBuffers bb = bin_buffers(p, ws);
+  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
+  pk = sorted_state(p, ws, 0);
+  const double ratio = (double)lat.ratio;
+  COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, q->s, bb, st); }));
+  COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, false, st); }));
+  COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter_pack(lat, bb, lagr, pk, st); }));
+  COLA_HIP(traced(p, kStDeposit, st, [&] {
+    return launch_deposit(lat, b, pk.s, bb, ws, (float)(ratio * ratio * ratio), st, nullptr, pk.lag);
+  }));
+  return fft_force(p, a, ws, st);
+}
+
+// One COLA step: PM force at a_i, merged kick, drift (eq. KDKALC).  The kick and drift
+// read the packed copy in tile order and write s, v back to the caller's arrays by
+// Lagrangian index; the arithmetic is the cola_run gather's, so both paths agree bit
+// for bit.
+int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st) {
   const StepRow& row = p->table[i];
-  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st, bp));
+  SortedState pk;
+  COLA_TRY(packed_mesh(p, q, row.a, ws, st, pk));
   const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
   KickArgs k{};
   k.alpha = (float)row.alpha;
@@ -329,23 +346,20 @@ int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_
   k.beta = (float)row.beta;
   k.dd1 = plain ? 0.0f : (float)row.dd1;
   k.dd2 = plain ? 0.0f : (float)row.dd2;
-  // The caller's Lagrangian-order arrays are read through the tile lists (each tile's
-  // records prefetched while its force tile is staged) and s, v are written back in
-  // place; the arithmetic is the tile-sorted cola_run gather's, so both paths agree
-  // bit for bit.
   const GatherArgs g = gather_args(p, ws);
   const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
   return hip_status(traced(p, kStGatherKickDrift, st, [&] {
-    return launch_gather_sorted(lattice(p), p->bins, lagr, lagr, bin_buffers(p, ws, bp.parity), kGatherKickDriftLag,
-                                g, k, st);
+    return launch_gather_sorted(lattice(p), p->bins, pk, lagr, bin_buffers(p, ws), kGatherKickDriftLag, g, k, st);
   }));
 }
 
-// Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops).
-int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out, float* ws, hipStream_t st,
-                BinPlan bp) {
+// Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops), as the closing step of
+// cola_run: the kick in tile order into the second workspace copy, then back to
+// Lagrangian order with L+ and the positions.
+int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out, float* ws, hipStream_t st) {
   const StepRow& row = p->table[p->cfg.n_steps];
-  COLA_TRY(pm_mesh(p, q->s, row.a, ws, st, bp));
+  SortedState pk;
+  COLA_TRY(packed_mesh(p, q, row.a, ws, st, pk));
   const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
   KickArgs k{};
   k.alpha = (float)row.alpha;
@@ -361,13 +375,10 @@ int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out
   g.s2 = q->s2;
   g.out_a = x_out;
   g.out_b = v_out;
-  // as the closing step of cola_run: the kick in tile order into a workspace copy,
-  // then back to Lagrangian order with L+ and the positions
-  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
-  const SortedState out = sorted_state(p, ws, 0);
+  const SortedState out = sorted_state(p, ws, 1);
   const Lattice lat = lattice(p);
   COLA_HIP(traced(p, kStFinish, st, [&] {
-    return launch_gather_sorted(lat, p->bins, lagr, out, bin_buffers(p, ws, bp.parity), kGatherFinish, g, k, st);
+    return launch_gather_sorted(lat, p->bins, pk, out, bin_buffers(p, ws), kGatherFinish, g, k, st);
   }));
   return hip_status(traced(p, kStUnsort, st, [&] { return launch_unsort(lat, out, g, k, st); }));
 }
@@ -569,7 +580,7 @@ size_t plan_bin_bytes(cola_plan_s* p) { return bin_workspace_bytes(cube(p->cfg.n
 int density_with_bins(cola_plan_s* p, const float* s, float* rho, void* bin_base, hipStream_t st) {
   if (p->trace) return COLA_ERR_INVALID;   // trace events are created on demand
   const BinBuffers bb = carve_bins(bin_base, cube(p->cfg.np), p->bins);
-  return deposit_with(p, s, rho, bb, st, BinPlan{});
+  return deposit_with(p, s, rho, bb, st);
 }
 
 }  // namespace cola
@@ -791,14 +802,14 @@ int cola_step(cola_plan p, int32_t i, const cola_particles* q, void* ws_, void* 
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
   if (i < 0 || i >= p->cfg.n_steps) return COLA_ERR_RANGE;
-  return step_impl(p, i, q, static_cast<float*>(ws_), (hipStream_t)stream, BinPlan{});
+  return step_impl(p, i, q, static_cast<float*>(ws_), (hipStream_t)stream);
 }
 
 int cola_finish(cola_plan p, const cola_particles* q, float* x_out, float* v_out, void* ws_, void* stream) {
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
   if (!x_out || !v_out) return COLA_ERR_INVALID;
-  return finish_impl(p, q, x_out, v_out, static_cast<float*>(ws_), (hipStream_t)stream, BinPlan{});
+  return finish_impl(p, q, x_out, v_out, static_cast<float*>(ws_), (hipStream_t)stream);
 }
 
 int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out, float* v_out, void* ws_,
@@ -878,11 +889,11 @@ int cola_run_checkpointed(cola_plan p, const float* w, const cola_particles* q, 
     float* dst = ckpt + (size_t)i * 3 * cube(p->cfg.np);
     COLA_HIP(traced(p, kStCheckpoint, st,
                     [&] { return hipMemcpyAsync(dst, q->s, bytes, hipMemcpyDeviceToDevice, st); }));
-    COLA_TRY(step_impl(p, i, q, ws, st, BinPlan{}));
+    COLA_TRY(step_impl(p, i, q, ws, st));
   }
   float* last = ckpt + (size_t)p->cfg.n_steps * 3 * cube(p->cfg.np);
   COLA_HIP(traced(p, kStCheckpoint, st, [&] { return hipMemcpyAsync(last, q->s, bytes, hipMemcpyDeviceToDevice, st); }));
-  return finish_impl(p, q, x_out, v_out, ws, st, BinPlan{});
+  return finish_impl(p, q, x_out, v_out, ws, st);
 }
 
 int cola_adjoint_workspace_bytes(cola_plan p, size_t* bytes) {

@@ -178,8 +178,8 @@ enum GatherMode : int {
   kGatherKickDrift = 1,     // v += alpha (F - t2d1 s1 - t2d2 s2); s += beta v + dd1 s1 + dd2 s2, written
                             // packed in this step's tile order and binned for the next step
   kGatherFinish = 2,        // the kick only, written packed for launch_unsort (x, L+)
-  kGatherKickDriftLag = 3,  // kick and drift of the caller's Lagrangian-order arrays in place
-                            // (src = dst = SoA s, v, s1, s2; no binning)
+  kGatherKickDriftLag = 3,  // kick and drift, s and v written to the caller's Lagrangian-order arrays
+                            // (dst SoA, by each record's Lagrangian index; no binning)
 };
 struct GatherArgs {
   const float* g0;
@@ -208,6 +208,10 @@ struct SortedState {
   float* s2;
   int* lag;
 };
+// The scatter of the public step: idx becomes the identity and dst (packed) receives, at
+// each particle's tile-sorted slot, its record from the caller's Lagrangian-order SoA
+// arrays src (src.lag == nullptr).
+hipError_t launch_bin_scatter_pack(Lattice lat, BinBuffers bb, SortedState src, SortedState dst, hipStream_t st);
 // Gather + kick over the tile lists bb.idx (slots of src).  kGatherKickDrift writes
 // the kicked and drifted record of list position j to slot j of the packed dst
 // (ordered by this step's tiles) and bins it for the next step (bb.count_next,

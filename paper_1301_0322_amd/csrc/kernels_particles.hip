@@ -294,6 +294,34 @@ __global__ __launch_bounds__(kPartThreads) void k_bin_scatter(long npart, const 
   idx[offset[kr.x] + kr.y] = (int)p;
 }
 
+// The scatter of the public step: besides its list entry (the identity: slot j holds the
+// particle listed at j), each particle's record is written packed to its tile-sorted slot
+// j = offset[key] + rank from the caller's Lagrangian-order arrays, which are read in
+// order; a wave's particles share few keys, so its writes land in runs of slots.
+__global__ __launch_bounds__(kPartThreads) void k_bin_scatter_pack(long npart, const int2* __restrict__ key_rank,
+                                                                   const int* __restrict__ offset,
+                                                                   int* __restrict__ idx, SortedState src,
+                                                                   SortedState dst) {
+  const long p = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  if (p >= npart) return;
+  const int2 kr = key_rank[p];
+  const long j = offset[kr.x] + kr.y;
+  float a[12];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    a[d] = src.s[d * npart + p];
+    a[3 + d] = src.v[d * npart + p];
+    a[6 + d] = src.s1[d * npart + p];
+    a[9 + d] = src.s2[d * npart + p];
+  }
+  float4* q = reinterpret_cast<float4*>(dst.s);
+  q[j] = make_float4(a[0], a[1], a[2], a[3]);
+  q[npart + j] = make_float4(a[4], a[5], a[6], a[7]);
+  q[2 * npart + j] = make_float4(a[8], a[9], a[10], a[11]);
+  dst.lag[j] = (int)p;
+  idx[j] = (int)j;
+}
+
 struct TileGeom {
   int bin;
   int lo[3];
@@ -814,7 +842,8 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
         vf[d] = v;
       }
       if constexpr (MODE == kGatherKickDriftLag) {
-        // the caller's arrays, in place: each particle is read and written by one lane
+        // the caller's Lagrangian-order arrays (when src is the same arrays, each
+        // particle is read and written by one lane)
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           dst.s[d * n + r.lag] = snew[d];
@@ -984,6 +1013,13 @@ hipError_t launch_bin_scan(Bins b, BinBuffers bb, bool clear_next, hipStream_t s
   return hipGetLastError();
 }
 
+hipError_t launch_bin_scatter_pack(Lattice lat, BinBuffers bb, SortedState src, SortedState dst, hipStream_t st) {
+  if (src.lag || !dst.s || !dst.lag || reinterpret_cast<uintptr_t>(dst.s) % 16 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_bin_scatter_pack, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat.npart,
+                     bb.key_rank, bb.offset, bb.idx, src, dst);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
   hipLaunchKernelGGL(k_bin_scatter, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat.npart, bb.key_rank,
                      bb.offset, bb.idx);
@@ -1036,8 +1072,8 @@ hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedStat
                                 GatherArgs a, KickArgs k, hipStream_t st) {
   if (mode != kGatherKickDrift && mode != kGatherFinish && mode != kGatherKickDriftLag) return hipErrorInvalidValue;
   if (mode == kGatherKickDriftLag) {
-    // dst is the caller's SoA arrays (s, v) in Lagrangian order, and so is src
-    if (!dst.s || !dst.v || dst.lag || src.lag) return hipErrorInvalidValue;
+    // dst is the caller's SoA arrays (s, v) in Lagrangian order
+    if (!dst.s || !dst.v || dst.lag) return hipErrorInvalidValue;
   } else if (!dst.s || !dst.lag || reinterpret_cast<uintptr_t>(dst.s) % 16 != 0) {
     // dst is packed: 12 n floats from dst.s, 16-byte aligned, and n ints of lag
     return hipErrorInvalidValue;
