@@ -200,6 +200,89 @@ def rocprof_trace_summary(directory: str, per_dispatch=("k_deposit_tiles", "k_ga
     return "\n".join(lines)
 
 
+def rocprof_busy_summary(directory: str, gap_us: float = 2000.0, min_dispatches: int = 200) -> str:
+    """GPU-busy fraction of each launch window of a kernel trace: dispatches are split
+    into windows at idle gaps longer than gap_us (a host synchronisation between
+    launches); for each window with at least min_dispatches kernels, busy = the length
+    of the union of the kernel intervals, wall = last end - first start."""
+    rows = _csv_rows(directory, "kernel_trace.csv")
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    windows, cur, last_end = [], [], None
+    for a, b in iv:
+        if cur and a - last_end > gap_us * 1e3:
+            windows.append(cur)
+            cur = []
+        last_end = b if not cur else max(last_end, b)
+        cur.append((a, b))
+    if cur:
+        windows.append(cur)
+    lines = [f"source_digest: {csrc_digest()}", "",
+             f"{'window':>6} {'dispatches':>10} {'wall_ms':>10} {'busy_ms':>10} {'busy_frac':>9} {'sum_kernel_ms':>13}"]
+    for k, w in enumerate(windows):
+        if len(w) < min_dispatches:
+            continue
+        busy, s0, e0 = 0, None, None
+        for a, b in w:
+            if s0 is None or a > e0:
+                if s0 is not None:
+                    busy += e0 - s0
+                s0, e0 = a, b
+            else:
+                e0 = max(e0, b)
+        busy += e0 - s0
+        wall = max(b for _, b in w) - w[0][0]
+        tot = sum(b - a for a, b in w)
+        lines.append(f"{k:>6} {len(w):>10} {wall * 1e-6:>10.3f} {busy * 1e-6:>10.3f} {busy / wall:>9.3f} "
+                     f"{tot * 1e-6:>13.3f}")
+    return "\n".join(lines)
+
+
+def _counter_values(directory: str, counter: str):
+    """{short kernel name: [value per dispatch]} of one counter, and the values of the
+    256 MiB calibration copy (--copy-calibration)."""
+    out, calib = {}, []
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        if r["Counter_Name"] != counter:
+            continue
+        name = _short_kernel_name(r["Kernel_Name"])
+        out.setdefault(name, []).append(float(r["Counter_Value"]))
+        if "copyBuffer" in name:
+            calib.append(float(r["Counter_Value"]))
+    return out, calib
+
+
+def rocprof_hbm_summary(fetch_dir: str, write_dir: str, stage: str = "", tz: int = 32) -> str:
+    """HBM bytes per dispatch from a FETCH_SIZE run and a WRITE_SIZE run (KiB per
+    dispatch), each scaled so that the 256 MiB device-to-device calibration copy of the
+    same command reads and writes 256 MiB.  With stage, the key: value block that
+    read_traffic() reads for that stage's kernel; else a table of every kernel."""
+    fetch, fcal = _counter_values(fetch_dir, "FETCH_SIZE")
+    write, wcal = _counter_values(write_dir, "WRITE_SIZE")
+    kib = 256 * 1024
+    # the calibration copy is the only copy whose WRITE_SIZE is 256 MiB
+    wc = [v for v in wcal if abs(v - kib) < 0.01 * kib]
+    if not wc:
+        raise SystemExit("no 256 MiB calibration copy in the WRITE_SIZE run (use --copy-calibration)")
+    fc = [v for v in fcal if abs(2 * v - kib) < 0.05 * kib or abs(v - kib) < 0.05 * kib]
+    fscale, wscale = kib / fc[-1], kib / wc[-1]
+    hbm = {k: (sum(fetch[k]) / len(fetch[k]), sum(write[k]) / len(write[k]), len(fetch[k]))
+           for k in fetch if k in write}
+    lines = [f"fetch_scale: {fscale:.4f}", f"write_scale: {wscale:.4f}", f"source_digest: {csrc_digest()}", ""]
+    if stage:
+        name = STAGE_KERNEL[stage].format(tz=tz)
+        f, w, n = hbm[name]
+        tot = f * 1024 * fscale + w * 1024 * wscale
+        alg = stage_bytes(256, 512)[stage]
+        lines += [f"kernel: {name}", f"launches_counted: {n}", f"fetch_kib_per_launch: {f:.1f}",
+                  f"write_kib_per_launch: {w:.1f}", f"hbm_bytes_per_launch: {tot:.0f}",
+                  f"algorithmic_bytes_per_launch: {alg}", f"traffic_over_algorithmic: {tot / alg:.2f}"]
+    else:
+        lines.append(f"{'kernel':<52} {'dispatches':>10} {'fetch_KiB':>12} {'write_KiB':>12} {'hbm_GB':>9}")
+        for k, (f, w, n) in sorted(hbm.items(), key=lambda kv: -(kv[1][0] * fscale + kv[1][1] * wscale)):
+            lines.append(f"{k:<52} {n:>10} {f:>12.1f} {w:>12.1f} {(f * fscale + w * wscale) * 1024 / 1e9:>9.3f}")
+    return "\n".join(lines)
+
+
 def rocprof_pmc_summary(directory: str) -> str:
     """Mean value per dispatch of every collected counter, per kernel."""
     rows = _csv_rows(directory, "counter_collection.csv")
@@ -402,7 +485,20 @@ def main() -> int:
                     help="also copy 256 MiB device to device once (a known-size kernel for HBM byte counters)")
     ap.add_argument("--rocprof-trace", metavar="DIR", help="print the summary of a rocprofv3 kernel trace and exit")
     ap.add_argument("--rocprof-pmc", metavar="DIR", help="print the summary of a rocprofv3 --pmc run and exit")
+    ap.add_argument("--rocprof-busy", metavar="DIR",
+                    help="print the GPU-busy fraction of each launch window of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--rocprof-hbm", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print HBM bytes per dispatch from a FETCH_SIZE and a WRITE_SIZE run and exit")
+    ap.add_argument("--stage", default="", help="with --rocprof-hbm: the key: value block of this stage")
+    ap.add_argument("--ensemble-only", action="store_true",
+                    help="run only the 48-member ensemble (graph launches, then the same runs one by one)")
     args = ap.parse_args()
+    if args.rocprof_hbm:
+        print(rocprof_hbm_summary(*args.rocprof_hbm, stage=args.stage))
+        return 0
+    if args.rocprof_busy:
+        print(rocprof_busy_summary(args.rocprof_busy))
+        return 0
     if args.rocprof_trace:
         print(rocprof_trace_summary(args.rocprof_trace))
         return 0
@@ -421,6 +517,9 @@ def main() -> int:
 
     np_side, nm, box, seed, desc = CONFIGS[args.config]
     torch.cuda.set_device(0)
+    if args.ensemble_only:
+        print(json.dumps({"ensemble": bench_ensemble(torch.cuda.current_stream())}), flush=True)
+        return 0
     cfg = cola.Config(np=np_side, nm=nm, box=box)
     plan = cola.Plan(cfg)
     ws = plan.workspace()
@@ -481,6 +580,13 @@ def main() -> int:
         if i > 0:
             step_ms.append(a.elapsed_time(b))
     api_step_ms = float(np.median(step_ms))
+    # where a public step's time goes: the same calls with every kernel traced
+    plan.init_2lpt(w, p, ws)
+    plan.trace_enable(1)
+    for i in range(cfg.n_steps):
+        plan.step(i, p, ws)
+    api_stages = {k: round(v[0] / cfg.n_steps, 4) for k, v in plan.trace_read().items()}
+    plan.trace_enable(0)
 
     sb = stage_bytes(np_side, nm)
     per_run = {k: {"ms": ms / args.steps, "launches": n // args.steps, "ms_per_launch": ms / n}
@@ -530,7 +636,8 @@ def main() -> int:
                         / (HBM_PEAK_GBS * 1e9),
                         "timed": "the public cola_step call on the caller's Lagrangian-order arrays (bins from "
                                  "scratch each call), HIP events around each call, median over steps 1.."
-                                 f"{cfg.n_steps - 1} after cola_init_2lpt"}},
+                                 f"{cfg.n_steps - 1} after cola_init_2lpt",
+                        "stages_ms_per_call": api_stages}},
         "stages_per_run": per_run,
         "tuning": tuning,
     }
