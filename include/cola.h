@@ -244,6 +244,22 @@ int cola_plan_set_fft_tile(cola_plan plan, int32_t pass, int32_t width);
  * cola_workspace_bytes again afterwards.  Host-only. */
 int cola_plan_set_bin_depth(cola_plan plan, int32_t depth);
 
+/* Rotated planes for the nm^3 half spectrum between the y passes and the x pass of
+ * the force, 2LPT and adjoint transforms (a tuning knob; results are identical bit
+ * for bit either way, only the placement of rows in the workspace changes).  With
+ * on = 1, row y of x-plane x is kept at row (y + r x) mod nm, r the x pass's inner
+ * DFT length (32 for nm = 512 or 1024, 24 for 768).  The x pass reads one row of
+ * every plane, and without rotation those rows are a power-of-two plane stride apart
+ * (4 MB at nm = 1024), which concentrates them on few HBM channels.  on = 0 keeps
+ * plain planes, on = -1 restores the built-in default (rotated for nm >= 1024);
+ * other values give COLA_ERR_INVALID.  Transforms of length np (np != nm) use the
+ * default for np.  cola_fft_r2c / cola_fft_c2r and the density statistics always
+ * use plain planes.  Host-only. */
+int cola_plan_set_fft_rotation(cola_plan plan, int32_t on);
+/* The rotation in rows per plane that the plan uses for the nm mesh (0 = plain).
+ * Host-only. */
+int cola_plan_get_fft_rotation(cola_plan plan, int32_t *rows);
+
 /* Current tuning: y-pass and x-pass tile widths (0 = built-in default) and bin
  * depth.  Host-only. */
 int cola_plan_get_tuning(cola_plan plan, int32_t *y_width, int32_t *x_width, int32_t *bin_depth);

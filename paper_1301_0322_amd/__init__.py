@@ -63,6 +63,8 @@ _PROTOS = {
     "cola_fft_c2r": (ctypes.c_int, [_VP, ctypes.c_int32, _VP, _VP, _VP]),
     "cola_plan_set_fft_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "cola_plan_set_bin_depth": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "cola_plan_set_fft_rotation": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "cola_plan_get_fft_rotation": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "cola_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     "cola_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(ColaParticles), _VP, ctypes.c_size_t, _VP,
@@ -324,6 +326,17 @@ class Plan:
 
     def set_bin_depth(self, depth: int):
         _check("cola_plan_set_bin_depth", lib().cola_plan_set_bin_depth(self._c, depth))
+
+    def set_fft_rotation(self, on: int):
+        """Rotated planes between the y and x passes of the mesh transforms: 1 on, 0 off,
+        -1 the default."""
+        _check("cola_plan_set_fft_rotation", lib().cola_plan_set_fft_rotation(self._c, on))
+
+    def get_fft_rotation(self) -> int:
+        """Rows per plane of the rotation in use (0: plain planes)."""
+        r = ctypes.c_int32()
+        _check("cola_plan_get_fft_rotation", lib().cola_plan_get_fft_rotation(self._c, ctypes.byref(r)))
+        return r.value
 
     def get_tuning(self):
         y, x, tz = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

@@ -26,6 +26,7 @@ struct cola_plan_s {
   std::vector<float> lpt_tab;     // sqrt(P/dp^3) / (kf n^2 np^3) indexed by n^2
   Bins bins;                      // Eulerian tiles of the force mesh
   int fft_width[2] = {0, 0};      // columns per tile of the mesh-size y passes and x pass (0: default)
+  int fft_rot = -1;               // rotate the mesh-size half spectrum between y and x: 1 / 0 (-1: default)
   // stage tracing (hipEvent pairs around each launch, on the launch stream)
   int trace = 0;   // trace level: 0 off, 1 every kernel, 2 each cola_run step
   std::vector<hipEvent_t> ev_pool;
@@ -176,15 +177,23 @@ Lattice lattice(cola_plan p) {
   return l;
 }
 
-// Forward y pass (in place) over nf fields of an n^3 half-spectrum layout.
 int width_for(cola_plan p, int n, int pass) { return n == p->cfg.nm ? p->fft_width[pass] : 0; }
+// Row rotation of the half spectrum that the method's y -> x -> y chains hold between
+// their y and x passes (the public FFT and the spectrum analysis use plain planes).
+int rot_for(cola_plan p, int n) {
+  const bool on = (n == p->cfg.nm && p->fft_rot >= 0) ? p->fft_rot == 1 : fft_rot_default_on(n);
+  return on ? fft_rot_rows(n) : 0;
+}
 
-int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const float2* tw, hipStream_t st,
+// y pass (in place) over nf fields of an n^3 half-spectrum layout; the k-space side
+// (output of dir < 0, input of dir > 0) has its planes rotated by rot.
+int ypass(cola_plan p, int stage, int n, int dir, FieldPtrs f, int nf, const float2* tw, hipStream_t st, int rot,
           int reverse = 0) {
   const long h = n / 2;
   const int w = width_for(p, n, 0);
-  return hip_status(traced(
-      p, stage, st, [&] { return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, w, st, reverse); }));
+  return hip_status(traced(p, stage, st, [&] {
+    return launch_col(n, dir, f, f, nf, n, (long)n * h, h, (int)h, tw, w, rot, st, reverse);
+  }));
 }
 
 // Workspace: four real nm^3 meshes (the three force components and the scalar field
@@ -247,7 +256,8 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   // The y pass walks the rows the z pass wrote last first, and each force field goes
   // through its y and z inverse passes back to back (the z pass again walking
   // backwards), so those passes start on data still held by the memory-side cache.
-  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g0}), 1, tw, st, 1));
+  const int rot = rot_for(p, n);
+  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g0}), 1, tw, st, rot, 1));
   const double kf = 2.0 * M_PI / p->cfg.box;
   MulArgs m{};
   m.c = (float)(1.5 * p->cfg.omega_m * a / (kf * (double)r));
@@ -259,7 +269,7 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   float* g3 = ws + 3 * r;
   COLA_HIP(traced(p, kStXPoisson, st, [&] {
     return launch_xmul(n, kMulGradPair, reinterpret_cast<float2*>(g0), fields({g0, g3}), 2, m, tw,
-                       p->fft_width[1], st);
+                       p->fft_width[1], rot, st);
   }));
   EpiArgs e{};
   e.scale = 1.0f;
@@ -269,7 +279,8 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   // both of its outputs together from their heads
   COLA_HIP(traced(p, kStYInvPair, st, [&] {
     return launch_col_pair(n, reinterpret_cast<const float2*>(g3), reinterpret_cast<float2*>(g2),
-                           reinterpret_cast<float2*>(g1), n, (long)n * h, h, h, tw, width_for(p, n, 0), st, 1);
+                           reinterpret_cast<float2*>(g1), n, (long)n * h, h, h, tw, width_for(p, n, 0), rot, st,
+                           1);
   }));
   e.reverse = 0;
   e.deriv = 2;   // field 1 (g2): the z component
@@ -278,7 +289,7 @@ int fft_force(cola_plan p, double a, float* ws, hipStream_t st) {
   }));
   e.deriv = 0;
   e.reverse = 1;
-  COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0}), 1, tw, st));
+  COLA_TRY(ypass(p, kStYInv, n, 1, fields({g0}), 1, tw, st, rot));
   COLA_HIP(traced(p, kStZInv, st, [&] {
     return launch_zinv(n, fields({g0}), fields({g0}), 1, (long)n * n, tw, kEpiStore, e, st);
   }));
@@ -430,12 +441,12 @@ int fwd_zy(cola_plan p, int stage, int n, std::initializer_list<float*> f, const
   for (float* x : f)
     COLA_HIP(traced(p, stage, st,
                     [&] { return launch_zfwd(n, x, reinterpret_cast<float2*>(x), (long)n * n, tw, st); }));
-  return ypass(p, stage, n, -1, fields(f), (int)f.size(), tw, st);
+  return ypass(p, stage, n, -1, fields(f), (int)f.size(), tw, st, rot_for(p, n));
 }
 
 // y and z inverse passes of one field, in place (scale 1).
 int inv_yz(cola_plan p, int stage, int n, float* x, const float2* tw, hipStream_t st) {
-  COLA_TRY(ypass(p, stage, n, 1, fields({x}), 1, tw, st));
+  COLA_TRY(ypass(p, stage, n, 1, fields({x}), 1, tw, st, rot_for(p, n)));
   EpiArgs e{};
   e.scale = 1.0f;
   return hip_status(traced(p, stage, st, [&] {
@@ -495,7 +506,7 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
     m.c = (float)(1.5 * p->cfg.omega_m * row.a / (kf * (double)cube(nm)));
     COLA_HIP(traced(p, kStAdjFft, st, [&] {
       return launch_xmul_adj(nm, kMulGrad, fields({L.amesh[0], L.amesh[1], L.amesh[2]}), 3,
-                             reinterpret_cast<float2*>(L.amesh[0]), m, tw, st);
+                             reinterpret_cast<float2*>(L.amesh[0]), m, tw, rot_for(p, nm), st);
     }));
     COLA_TRY(inv_yz(p, kStAdjFft, nm, L.amesh[0], tw, st));
     // lam_s += alpha [ (1/dx) grad(mu . g) + (1/dx) grad(rbar) ]
@@ -525,16 +536,17 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
   for (int k = 0; k < 10; ++k) sc[k] = L.lpt + k * n;
   COLA_HIP(traced(p, kStAdjLpt, st,
                   [&] { return launch_zfwd(np_, w, reinterpret_cast<float2*>(sc[9]), (long)np_ * np_, twp, st); }));
-  COLA_TRY(ypass(p, kStAdjLpt, np_, -1, fields({sc[9]}), 1, twp, st));
+  const int rot_p = rot_for(p, np_);
+  COLA_TRY(ypass(p, kStAdjLpt, np_, -1, fields({sc[9]}), 1, twp, st, rot_p));
   MulArgs ml{};
   ml.kf = (float)kf;
   ml.tab = p->d_lpt_tab;
   const FieldPtrs all9 = fields({sc[0], sc[1], sc[2], sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]});
   COLA_HIP(traced(p, kStAdjLpt, st, [&] {
-    return launch_xmul(np_, kMulLpt1, reinterpret_cast<float2*>(sc[9]), all9, 9, ml, twp, 0, st);
+    return launch_xmul(np_, kMulLpt1, reinterpret_cast<float2*>(sc[9]), all9, 9, ml, twp, 0, rot_p, st);
   }));
   const FieldPtrs phi = fields({sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]});
-  COLA_TRY(ypass(p, kStAdjLpt, np_, 1, phi, 6, twp, st));
+  COLA_TRY(ypass(p, kStAdjLpt, np_, 1, phi, 6, twp, st, rot_p));
   EpiArgs e1{};
   e1.scale = 1.0f;
   COLA_HIP(traced(p, kStAdjLpt, st,
@@ -546,7 +558,7 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
   m2.c = (float)(-1.0 / (kf * (double)n));
   COLA_HIP(traced(p, kStAdjLpt, st, [&] {
     return launch_xmul_adj(np_, kMulGrad, fields({l2[0], l2[1], l2[2]}), 3, reinterpret_cast<float2*>(sc[9]), m2,
-                           twp, st);
+                           twp, rot_p, st);
   }));
   COLA_TRY(inv_yz(p, kStAdjLpt, np_, sc[9], twp, st));
   // tau_ab = dS/dphi_ab^T sigma, in place over phi
@@ -559,9 +571,9 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
   COLA_TRY(fwd_zy(p, kStAdjLpt, np_, {sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]}, twp, st));
   const FieldPtrs in9 = fields({l1[0], l1[1], l1[2], sc[3], sc[4], sc[5], sc[6], sc[7], sc[8]});
   COLA_HIP(traced(p, kStAdjLpt, st, [&] {
-    return launch_xmul_adj(np_, kMulLpt1, in9, 9, reinterpret_cast<float2*>(sc[9]), ml, twp, st);
+    return launch_xmul_adj(np_, kMulLpt1, in9, 9, reinterpret_cast<float2*>(sc[9]), ml, twp, rot_p, st);
   }));
-  COLA_TRY(ypass(p, kStAdjLpt, np_, 1, fields({sc[9]}), 1, twp, st));
+  COLA_TRY(ypass(p, kStAdjLpt, np_, 1, fields({sc[9]}), 1, twp, st, rot_p));
   EpiArgs e2{};
   e2.scale = 1.0f;
   return hip_status(traced(p, kStAdjLpt, st, [&] {
@@ -690,7 +702,8 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
   // delta_k and its derivatives: s1 into q->s1, Hessian into q->s and q->v.
   COLA_HIP(traced(p, kStLptZFwd, st,
                   [&] { return launch_zfwd(n, w, reinterpret_cast<float2*>(w0), (long)n * n, tw, st); }));
-  COLA_TRY(ypass(p, kStLptYFwd, n, -1, fields({w0}), 1, tw, st));
+  const int rot = rot_for(p, n);
+  COLA_TRY(ypass(p, kStLptYFwd, n, -1, fields({w0}), 1, tw, st, rot));
   MulArgs m{};
   const double kf = 2.0 * M_PI / p->cfg.box;
   m.kf = (float)kf;
@@ -699,8 +712,8 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
   float* hs[6] = {q->s, q->s + r, q->s + 2 * r, q->v, q->v + r, q->v + 2 * r};
   FieldPtrs outs = fields({s1[0], s1[1], s1[2], hs[0], hs[1], hs[2], hs[3], hs[4], hs[5]});
   COLA_HIP(traced(p, kStLptX, st,
-                  [&] { return launch_xmul(n, kMulLpt1, reinterpret_cast<float2*>(w0), outs, 9, m, tw, 0, st); }));
-  COLA_TRY(ypass(p, kStLptYInv, n, 1, outs, 9, tw, st));
+                  [&] { return launch_xmul(n, kMulLpt1, reinterpret_cast<float2*>(w0), outs, 9, m, tw, 0, rot, st); }));
+  COLA_TRY(ypass(p, kStLptYInv, n, 1, outs, 9, tw, st, rot));
   EpiArgs e{};
   e.scale = 1.0f;
   FieldPtrs f_s1 = fields({s1[0], s1[1], s1[2]});
@@ -713,14 +726,14 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
   // second order: s2_k = -i k S_k / k^2
   COLA_HIP(traced(p, kStLptZFwd, st,
                   [&] { return launch_zfwd(n, w0, reinterpret_cast<float2*>(w0), (long)n * n, tw, st); }));
-  COLA_TRY(ypass(p, kStLptYFwd, n, -1, fields({w0}), 1, tw, st));
+  COLA_TRY(ypass(p, kStLptYFwd, n, -1, fields({w0}), 1, tw, st, rot));
   float* s2[3] = {q->s2, q->s2 + r, q->s2 + 2 * r};
   FieldPtrs f_s2 = fields({s2[0], s2[1], s2[2]});
   MulArgs m2{};
   m2.c = (float)(-1.0 / (kf * (double)r));
   COLA_HIP(traced(p, kStLptX, st,
-                  [&] { return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(w0), f_s2, 3, m2, tw, 0, st); }));
-  COLA_TRY(ypass(p, kStLptYInv, n, 1, f_s2, 3, tw, st));
+                  [&] { return launch_xmul(n, kMulGrad, reinterpret_cast<float2*>(w0), f_s2, 3, m2, tw, 0, rot, st); }));
+  COLA_TRY(ypass(p, kStLptYInv, n, 1, f_s2, 3, tw, st, rot));
   // s2, then s = D1 s1 + D2 s2 and the initial velocity.
   EpiArgs ef{};
   ef.scale = 1.0f;
@@ -751,10 +764,10 @@ int fft_forward(cola_plan p, float* g, hipStream_t st) {
   const float2* tw = p->d_tw_nm;
   COLA_HIP(traced(p, kStZFwd, st,
                   [&] { return launch_zfwd(n, g, reinterpret_cast<float2*>(g), (long)n * n, tw, st); }));
-  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g}), 1, tw, st));
+  COLA_TRY(ypass(p, kStYFwd, n, -1, fields({g}), 1, tw, st, 0));
   // x: columns along x (stride n h) in tiles of kz at fixed y
   return hip_status(traced(p, kStAnalysis, st, [&] {
-    return launch_col(n, -1, fields({g}), fields({g}), 1, n, h, (long)n * h, (int)h, tw, p->fft_width[1], st);
+    return launch_col(n, -1, fields({g}), fields({g}), 1, n, h, (long)n * h, (int)h, tw, p->fft_width[1], 0, st);
   }));
 }
 
@@ -917,11 +930,11 @@ int cola_fft_r2c(cola_plan p, int32_t n, const float* in, float* out, void* stre
   const float2* tw = twiddle_for(p, n);
   COLA_HIP(traced(p, kStFft, st,
                   [&] { return launch_zfwd(n, in, reinterpret_cast<float2*>(out), (long)n * n, tw, st); }));
-  COLA_TRY(ypass(p, kStFft, n, -1, fields({out}), 1, tw, st));
+  COLA_TRY(ypass(p, kStFft, n, -1, fields({out}), 1, tw, st, 0));
   const long h = n / 2;
   FieldPtrs f = fields({out});
   return hip_status(
-      traced(p, kStFft, st, [&] { return launch_col(n, -1, f, f, 1, n, h, (long)n * h, (int)h, tw, 0, st); }));
+      traced(p, kStFft, st, [&] { return launch_col(n, -1, f, f, 1, n, h, (long)n * h, (int)h, tw, 0, 0, st); }));
 }
 
 int cola_fft_c2r(cola_plan p, int32_t n, const float* in, float* out, void* stream) {
@@ -934,8 +947,8 @@ int cola_fft_c2r(cola_plan p, int32_t n, const float* in, float* out, void* stre
   FieldPtrs fi = fields({const_cast<float*>(in)});
   FieldPtrs fo = fields({out});
   COLA_HIP(
-      traced(p, kStFft, st, [&] { return launch_col(n, 1, fi, fo, 1, n, h, (long)n * h, (int)h, tw, 0, st); }));
-  COLA_TRY(ypass(p, kStFft, n, 1, fo, 1, tw, st));
+      traced(p, kStFft, st, [&] { return launch_col(n, 1, fi, fo, 1, n, h, (long)n * h, (int)h, tw, 0, 0, st); }));
+  COLA_TRY(ypass(p, kStFft, n, 1, fo, 1, tw, st, 0));
   EpiArgs e{};
   e.scale = (float)(1.0 / (double)cube(n));
   return hip_status(
@@ -953,6 +966,18 @@ int cola_plan_set_bin_depth(cola_plan p, int32_t tz) {
   if (!p || (tz != 8 && tz != 16 && tz != 32 && tz != 64)) return COLA_ERR_INVALID;
   if (p->cfg.nm % tz) return COLA_ERR_UNSUPPORTED_SIZE;
   p->bins = make_bins(p->cfg.nm, tz);
+  return COLA_OK;
+}
+
+int cola_plan_set_fft_rotation(cola_plan p, int32_t on) {
+  if (!p || on < -1 || on > 1) return COLA_ERR_INVALID;
+  p->fft_rot = on;
+  return COLA_OK;
+}
+
+int cola_plan_get_fft_rotation(cola_plan p, int32_t* rot) {
+  if (!p || !rot) return COLA_ERR_INVALID;
+  *rot = rot_for(p, p->cfg.nm);
   return COLA_OK;
 }
 

@@ -212,6 +212,35 @@ struct Pencil {
       for (int j1 = 0; j1 < R1; ++j1) dst[elem(b, j2 + R2 * j1, stride)] = q[u][j1];
     }
   }
+  // COL tiles whose rows are not evenly spaced: element m of column b sits at
+  // src[row(m) + b], row(m) an element offset.
+  template <class RowF>
+  __device__ static void load_a_rows(float2 (&a)[R2], const float2* src, RowF row) {
+    static_assert(!ROW, "row maps are for column tiles");
+    int b, i1;
+    a_unit(b, i1);
+#pragma unroll
+    for (int i2 = 0; i2 < R2; ++i2) a[i2] = src[row(i1 + R1 * i2) + b];
+  }
+  template <class RowF>
+  __device__ static void store_a_rows(const float2 (&a)[R2], float2* dst, RowF row) {
+    static_assert(!ROW, "row maps are for column tiles");
+    int b, i1;
+    a_unit(b, i1);
+#pragma unroll
+    for (int i2 = 0; i2 < R2; ++i2) dst[row(i1 + R1 * i2) + b] = a[i2];
+  }
+  template <class RowF>
+  __device__ static void store_b_rows(const float2 (&q)[UB][R1], float2* dst, RowF row) {
+    static_assert(!ROW, "row maps are for column tiles");
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      int b, j2;
+      if (!b_unit(u, b, j2)) continue;
+#pragma unroll
+      for (int j1 = 0; j1 < R1; ++j1) dst[row(j2 + R2 * j1) + b] = q[u][j1];
+    }
+  }
 
   // A-layout (positions i1 + R1 i2) -> B-layout (positions j2 + R2 j1), sign S.
   // Destroys a.  The caller has the LDS exchange free on entry (a barrier since its last

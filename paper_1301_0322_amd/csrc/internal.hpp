@@ -65,9 +65,12 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 // Strided column pass (length n along inner_stride) over tiles of contiguous columns.
 // Tiles: outer index o in [0, n_outer) at outer_stride; columns [0, ncols) contiguous.
 // width: columns per tile (4, 8 or 16; 0 picks the default for n).
+// rot (0 <= rot < n): for y passes (o = x plane, inner_stride = one row), the k-space
+// side (output of dir < 0, input of dir > 0) is a rotated half spectrum: row y of plane
+// x at row (y + rot x) mod n.  0 for the plain layout and for passes along x.
 // reverse: blocks take the tiles from the last to the first.
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nfields, int n_outer,
-                      long outer_stride, long inner_stride, int ncols, const float2* tw, int width,
+                      long outer_stride, long inner_stride, int ncols, const float2* tw, int width, int rot,
                       hipStream_t st, int reverse = 0);
 // Shell statistics of one or two half spectra (b may be null) into out[6][n/2]
 // (doubles, row r, shell s = round(|n|) for 1 <= s < n/2; s = 0 stays zero): mode
@@ -77,15 +80,22 @@ hipError_t launch_shell_stats(int n, const float2* a, const float2* b, double* p
                               double* out, hipStream_t st);
 // Inverse column pass of one field with two outputs: out_d = inverse transform of
 // i n X (n the signed mode number along the column) and out_p = inverse transform of
-// X.  The three buffers are distinct.
+// X.  The three buffers are distinct.  in is rotated by rot as the input of an
+// inverse y pass of launch_col; the outputs are plain.
 hipError_t launch_col_pair(int n, const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
-                           long inner_stride, int ncols, const float2* tw, int width, hipStream_t st,
+                           long inner_stride, int ncols, const float2* tw, int width, int rot, hipStream_t st,
                            int reverse = 0);
 // x pass with the k-space multiplier: forward x transform of `in`, multiply, inverse
-// x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row.
-// kMulGrad requires nout = 3, kMulGradPair 2, kMulLpt1 1..9.
+// x transform into each of nout outputs.  Layout [x][y][kz] with n/2 kz per row, the
+// rows of every x plane rotated by rot (input and outputs alike), rot a multiple of
+// fft_rot_rows(n).  kMulGrad requires nout = 3, kMulGradPair 2, kMulLpt1 1..9.
 hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m,
-                       const float2* tw, int width, hipStream_t st);
+                       const float2* tw, int width, int rot, hipStream_t st);
+// Rows per plane by which a rotated half spectrum of transform length n is rotated
+// (the x passes' R2, so that a thread's rows share one stride), and whether plans
+// rotate by default at length n.
+int fft_rot_rows(int n);
+bool fft_rot_default_on(int n);
 // Whether `width` columns per tile is a valid strided-pass shape for length n.
 bool fft_width_supported(int n, int width);
 
@@ -249,9 +259,9 @@ hipError_t launch_hessian_adjoint(long n, const float* sigma, HessPtrs h, hipStr
 // Transposed x pass: forward x transform of each of nin inputs, multiply by the
 // complex conjugate of the mode's multiplier for that input, sum, inverse x
 // transform into out.  kMulGrad: nin = 3 (conj of c i n_j / n^2); kMulLpt1: nin = 9
-// (conj of the s1_j and phi_ab multipliers).
+// (conj of the s1_j and phi_ab multipliers).  Inputs and output rotated by rot.
 hipError_t launch_xmul_adj(int n, int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
-                           hipStream_t st);
+                           int rot, hipStream_t st);
 
 hipError_t launch_noise(uint64_t seed, float* w, long count, hipStream_t st);
 

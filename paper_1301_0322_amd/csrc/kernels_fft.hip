@@ -6,6 +6,17 @@
 // (n/2 complex per row): the kz = n/2 plane is never stored because every
 // k-space operator of the method zeroes Nyquist-index modes.
 //
+// Rotated planes: between the y passes and the x pass the half spectrum may be held
+// with the rows of every x-plane rotated by `rot` rows per plane: row y of plane x at
+// row (y + rot x) mod n.  The x pass reads one row from each of the n planes; with
+// rot = 0 those rows lie exactly n^2/2 complex apart (4 MB at n = 1024), a power-of-
+// two stride that sends a column's loads to the same few HBM channels, and a rotation
+// spreads them.  A y pass owns whole columns of a plane, so the forward one stores
+// rotated and the inverse one loads rotated, in place.  The x passes take rot as a
+// multiple of R2 = n / R1 (their register DFT split n = R1 R2): a thread holds planes
+// x = i1 + R1 i2, whose rows (y + rot i1) mod n then do not depend on i2, so each
+// thread's 2 R2 loads and stores keep one stride.
+//
 // Passes (each reads and writes every element once, HBM-bound):
 //   z forward   rows of n reals -> n/2 complex (half-length complex FFT + split)
 //   y / x       strided column FFTs over tiles of B contiguous kz columns
@@ -54,6 +65,12 @@ constexpr bool col_ok() {
 template <int N>
 constexpr int col_width_default() {
   return col_ok<N, 16>() ? 16 : col_ok<N, 8>() ? 8 : 4;
+}
+
+// Stored row of logical row y of x-plane x in a rotated half spectrum.
+template <int N>
+__device__ __forceinline__ int rot_row(int y, int x, int rot) {
+  return (int)((unsigned)(y + rot * x) % (unsigned)N);
 }
 
 __device__ __forceinline__ int pick_comp(int c, int nx, int ny, int nz) {
@@ -228,10 +245,13 @@ __global__ __launch_bounds__(ZHPencil<N>::T) void k_zinv_hess(FieldPtrs in, floa
 // reverse: blocks walk the tiles from the last to the first, so a pass that follows
 // one which wrote the same array in ascending order starts on the data written last
 // (still in the memory-side cache).
+// rot: the k-space side (the output of a forward pass, the input of an inverse one) is
+// a rotated half spectrum whose plane index is the outer index o (y passes only).
 template <int N, int B, int S>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, FieldPtrs out, long outer_stride,
                                                                 long inner_stride, int ntiles_c,
-                                                                const float2* __restrict__ tw, int reverse) {
+                                                                const float2* __restrict__ tw, int reverse,
+                                                                int rot) {
   using P = Pencil<N, B, false>;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
@@ -240,26 +260,29 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, 
   const int tc = blk % ntiles_c;
   const long o = blk / ntiles_c;
   const long origin = o * outer_stride + (long)tc * B;
+  const int rot_in = S > 0 ? rot : 0, rot_out = S < 0 ? rot : 0;
   float2 a[P::R2];
-  P::load_a(a, in.p[f] + origin, inner_stride);
+  P::load_a_rows(a, in.p[f] + origin, [&](int m) { return (long)rot_row<N>(m, (int)o, rot_in) * inner_stride; });
   load_twiddles(stw, tw, N);
   __syncthreads();
   float2 q[P::UB][P::R1];
   P::template fwd_like<S, 1>(a, q, ex, stw);
-  P::store_b(q, out.p[f] + origin, inner_stride);
+  P::store_b_rows(q, out.p[f] + origin, [&](int m) { return (long)rot_row<N>(m, (int)o, rot_out) * inner_stride; });
 }
 
 // Inverse column pass with two outputs from one tile of columns: out_d gets the
 // inverse transform of i n X (n = m for m <= n/2, else m - n, m the position along
 // the column) and out_p that of X; neither may alias in.  Each tile is read by two
 // blocks, one per output, 8 block indices apart (the same XCD, dispatched together),
-// so the second read is served by that XCD's L2.
+// so the second read is served by that XCD's L2.  in may be a rotated half spectrum
+// (rot, plane index o); the outputs are not rotated.
 template <int N, int B>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const float2* __restrict__ in,
                                                                      float2* __restrict__ out_p,
                                                                      float2* __restrict__ out_d, long outer_stride,
                                                                      long inner_stride, int ntiles_c, long ntiles,
-                                                                     const float2* __restrict__ tw, int reverse) {
+                                                                     const float2* __restrict__ tw, int reverse,
+                                                                     int rot) {
   using P = Pencil<N, B, false>;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
@@ -278,7 +301,7 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const flo
   const long o = tile / ntiles_c;
   const long origin = o * outer_stride + (long)tc * B;
   float2 a[P::R2];
-  P::load_a(a, in + origin, inner_stride);
+  P::load_a_rows(a, in + origin, [&](int m) { return (long)rot_row<N>(m, (int)o, rot) * inner_stride; });
   load_twiddles(stw, tw, N);
   if (deriv) {
     int b, i1;
@@ -301,20 +324,44 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const flo
 // Modes with nx or ny equal to n/2, and the k = 0 mode, get multiplier 0.
 // The forward spectrum is held in registers, pre-scaled by the part of the multiplier
 // shared by all outputs (c / n^2, or tab[n^2]); each output then applies its own
-// factor and is inverse transformed.
+// factor and is inverse transformed.  Input and outputs are rotated half spectra
+// (rot); row x of the tile is row rot_row(y, x) of plane x.  At n >= 1024, where a
+// field is many times the memory-side cache, consecutive blocks take consecutive y
+// of one kz tile, so the rows that one wave of blocks reads in a plane lie together.
 // ---------------------------------------------------------------------------------
+// Offset of this thread's first element (plane i1, A layout) in a rotated half spectrum
+// at row y, column kz0; the thread's planes i1 + R1 i2 follow at stride n^2/2.
+template <class P, int N>
+__device__ __forceinline__ long xmul_origin(int y, int kz0, int rot) {
+  static_assert(P::R1 * P::R2 == N, "x pass tiles are one transform of length n");
+  int b, i1;
+  P::a_unit(b, i1);
+  return (long)rot_row<N>(y, i1, rot) * (N / 2) + kz0;
+}
+
+template <int N>
+__device__ __forceinline__ void xmul_tile(int nt, int& tc, int& y) {
+  if constexpr (N >= 1024) {
+    tc = blockIdx.x / N;
+    y = blockIdx.x % N;
+  } else {
+    tc = blockIdx.x % nt;
+    y = blockIdx.x / nt;
+  }
+}
+
 template <int N, int B, int MODE>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul(const float2* in, FieldPtrs out, int nout,
-                                                                 MulArgs ma, const float2* __restrict__ tw) {
+                                                                 MulArgs ma, const float2* __restrict__ tw, int rot) {
   using P = Pencil<N, B, false>;
   constexpr int H = N / 2;
   constexpr int NT = H / B;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
-  const int tc = blockIdx.x % NT;
-  const int y = blockIdx.x / NT;
+  int tc, y;
+  xmul_tile<N>(NT, tc, y);
   const long inner = (long)N * H;
-  const long origin = (long)y * H + tc * B;
+  const long origin = xmul_origin<P, N>(y, tc * B, rot);
   float2 a[P::R2];
   P::load_a(a, in + origin, inner);
   load_twiddles(stw, tw, N);
@@ -386,17 +433,17 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul(const float2*
 // ---------------------------------------------------------------------------------
 template <int N, int B, int MODE>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_xmul_adj(FieldPtrs in, int nin, float2* out, MulArgs ma,
-                                                                     const float2* __restrict__ tw) {
+                                                                     const float2* __restrict__ tw, int rot) {
   using P = Pencil<N, B, false>;
   constexpr int H = N / 2;
   constexpr int NT = H / B;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
   load_twiddles(stw, tw, N);
-  const int tc = blockIdx.x % NT;
-  const int y = blockIdx.x / NT;
+  int tc, y;
+  xmul_tile<N>(NT, tc, y);
   const long inner = (long)N * H;
-  const long origin = (long)y * H + tc * B;
+  const long origin = xmul_origin<P, N>(y, tc * B, rot);
   const int ny = (y <= H) ? y : y - N;
   const bool ny_ok = (y != H);
   float2 acc[P::UB][P::R1];
@@ -499,7 +546,7 @@ static hipError_t zinv_hess_t(FieldPtrs in, float* out, long nrows, const float2
 
 template <int N, int B>
 static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                         long inner_stride, int ncols, const float2* tw, int reverse, hipStream_t st) {
+                         long inner_stride, int ncols, const float2* tw, int reverse, int rot, hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
     if (ncols % B) return hipErrorInvalidValue;
     constexpr int T = Pencil<N, B, false>::T;
@@ -507,10 +554,10 @@ static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_out
     dim3 grid((unsigned)((long)n_outer * ntc), nf);
     if (dir < 0)
       hipLaunchKernelGGL((k_col<N, B, -1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw,
-                         reverse);
+                         reverse, rot);
     else
       hipLaunchKernelGGL((k_col<N, B, 1>), grid, dim3(T), 0, st, in, out, outer_stride, inner_stride, ntc, tw,
-                         reverse);
+                         reverse, rot);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -519,25 +566,26 @@ static hipError_t col_tb(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_out
 
 template <int N>
 static hipError_t col_t(int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                        long inner_stride, int ncols, const float2* tw, int width, int reverse, hipStream_t st) {
+                        long inner_stride, int ncols, const float2* tw, int width, int reverse, int rot,
+                        hipStream_t st) {
   switch (width ? width : col_width_default<N>()) {
-    case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
-    case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
-    case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    case 4: return col_tb<N, 4>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, rot, st);
+    case 8: return col_tb<N, 8>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, rot, st);
+    case 16: return col_tb<N, 16>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, reverse, rot, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int N, int B>
 static hipError_t col_pair_tb(const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
-                              long inner_stride, int ncols, const float2* tw, int reverse, hipStream_t st) {
+                              long inner_stride, int ncols, const float2* tw, int reverse, int rot, hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
     if (ncols % B) return hipErrorInvalidValue;
     constexpr int T = Pencil<N, B, false>::T;
     const int ntc = ncols / B;
     const long ntiles = (long)n_outer * ntc;
     hipLaunchKernelGGL((k_col_pair<N, B>), dim3((unsigned)(2 * ntiles)), dim3(T), 0, st, in, out_p, out_d,
-                       outer_stride, inner_stride, ntc, ntiles, tw, reverse);
+                       outer_stride, inner_stride, ntc, ntiles, tw, reverse, rot);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -546,31 +594,36 @@ static hipError_t col_pair_tb(const float2* in, float2* out_p, float2* out_d, in
 
 template <int N>
 static hipError_t col_pair_t(const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
-                             long inner_stride, int ncols, const float2* tw, int width, int reverse, hipStream_t st) {
+                             long inner_stride, int ncols, const float2* tw, int width, int reverse, int rot,
+                             hipStream_t st) {
   switch (width ? width : col_width_default<N>()) {
-    case 4: return col_pair_tb<N, 4>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
-    case 8: return col_pair_tb<N, 8>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
-    case 16: return col_pair_tb<N, 16>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, st);
+    case 4:
+      return col_pair_tb<N, 4>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, rot, st);
+    case 8:
+      return col_pair_tb<N, 8>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, rot, st);
+    case 16:
+      return col_pair_tb<N, 16>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, reverse, rot, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int N, int B>
 static hipError_t xmul_tb(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
-                          hipStream_t st) {
+                          int rot, hipStream_t st) {
   if constexpr (col_ok<N, B>()) {
     constexpr int T = Pencil<N, B, false>::T;
+    if (rot % Pencil<N, B, false>::R2) return hipErrorInvalidValue;
     if (mode == kMulGrad ? nout != 3
         : mode == kMulGradPair ? nout != 2
         : (mode != kMulLpt1 || nout < 1 || nout > kMaxFields))
       return hipErrorInvalidValue;
     dim3 grid(N * ((N / 2) / B));
     if (mode == kMulGrad)
-      hipLaunchKernelGGL((k_xmul<N, B, kMulGrad>), grid, dim3(T), 0, st, in, out, nout, m, tw);
+      hipLaunchKernelGGL((k_xmul<N, B, kMulGrad>), grid, dim3(T), 0, st, in, out, nout, m, tw, rot);
     else if (mode == kMulGradPair)
-      hipLaunchKernelGGL((k_xmul<N, B, kMulGradPair>), grid, dim3(T), 0, st, in, out, nout, m, tw);
+      hipLaunchKernelGGL((k_xmul<N, B, kMulGradPair>), grid, dim3(T), 0, st, in, out, nout, m, tw, rot);
     else
-      hipLaunchKernelGGL((k_xmul<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, out, nout, m, tw);
+      hipLaunchKernelGGL((k_xmul<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, out, nout, m, tw, rot);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
@@ -583,28 +636,31 @@ constexpr int xmul_width() { return col_width_default<N>(); }
 
 template <int N>
 static hipError_t xmul_t(int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
-                         int width, hipStream_t st) {
+                         int width, int rot, hipStream_t st) {
   switch (width ? width : xmul_width<N>()) {
-    case 4: return xmul_tb<N, 4>(mode, in, out, nout, m, tw, st);
-    case 8: return xmul_tb<N, 8>(mode, in, out, nout, m, tw, st);
-    case 16: return xmul_tb<N, 16>(mode, in, out, nout, m, tw, st);
+    case 4: return xmul_tb<N, 4>(mode, in, out, nout, m, tw, rot, st);
+    case 8: return xmul_tb<N, 8>(mode, in, out, nout, m, tw, rot, st);
+    case 16: return xmul_tb<N, 16>(mode, in, out, nout, m, tw, rot, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int N>
 static hipError_t xmul_adj_t(int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
-                             hipStream_t st) {
-  // the transposed pass holds three inputs: 16 columns of 1024 would spill
-  constexpr int B = (N >= 1024 && xmul_width<N>() > 8) ? 8 : xmul_width<N>();
-  constexpr int T = Pencil<N, B, false>::T;
+                             int rot, hipStream_t st) {
+  // the transposed pass holds three inputs: 16 columns of 1024 would spill, and the
+  // nine-input LPT form spills with 16 columns of 768
+  constexpr int BG = (N >= 1024 && xmul_width<N>() > 8) ? 8 : xmul_width<N>();
+  constexpr int BL = (N >= 768 && BG > 8) ? 8 : BG;
+  if (rot % pencil_r2(N)) return hipErrorInvalidValue;
   if (mode != kMulGrad && mode != kMulLpt1) return hipErrorInvalidValue;
   if (mode == kMulGrad ? nin != 3 : (nin < 1 || nin > kMaxFields)) return hipErrorInvalidValue;
-  dim3 grid(N * ((N / 2) / B));
   if (mode == kMulGrad)
-    hipLaunchKernelGGL((k_xmul_adj<N, B, kMulGrad>), grid, dim3(T), 0, st, in, nin, out, m, tw);
+    hipLaunchKernelGGL((k_xmul_adj<N, BG, kMulGrad>), dim3(N * ((N / 2) / BG)), dim3(Pencil<N, BG, false>::T), 0, st,
+                       in, nin, out, m, tw, rot);
   else
-    hipLaunchKernelGGL((k_xmul_adj<N, B, kMulLpt1>), grid, dim3(T), 0, st, in, nin, out, m, tw);
+    hipLaunchKernelGGL((k_xmul_adj<N, BL, kMulLpt1>), dim3(N * ((N / 2) / BL)), dim3(Pencil<N, BL, false>::T), 0, st,
+                       in, nin, out, m, tw, rot);
   return hipGetLastError();
 }
 
@@ -630,6 +686,11 @@ bool fft_width_supported(int n, int width) {
       return false;
   }
 }
+
+int fft_rot_rows(int n) { return fft_size_supported(n) ? pencil_r2(n) : 0; }
+// Rotated where the plane stride is 4 MB or more (n >= 1024): there copies with the x
+// pass's access pattern move 2.7 TB/s over plain planes and 3.7 TB/s over rotated ones.
+bool fft_rot_default_on(int n) { return n >= 1024; }
 
 hipError_t launch_zfwd(int n, const float* in, float2* out, long nrows, const float2* tw, hipStream_t st) {
   switch (n) {
@@ -670,11 +731,13 @@ hipError_t launch_zinv_hessian(int n, FieldPtrs in, float* out, long nrows, cons
 }
 
 hipError_t launch_col(int n, int dir, FieldPtrs in, FieldPtrs out, int nf, int n_outer, long outer_stride,
-                      long inner_stride, int ncols, const float2* tw, int width, hipStream_t st, int reverse) {
+                      long inner_stride, int ncols, const float2* tw, int width, int rot, hipStream_t st,
+                      int reverse) {
+  if (rot < 0 || rot >= n) return hipErrorInvalidValue;
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, st);
+    return col_t<N>(dir, in, out, nf, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, rot, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:
@@ -780,12 +843,14 @@ hipError_t launch_shell_stats(int n, const float2* a, const float2* b, double* p
 }
 
 hipError_t launch_col_pair(int n, const float2* in, float2* out_p, float2* out_d, int n_outer, long outer_stride,
-                           long inner_stride, int ncols, const float2* tw, int width, hipStream_t st, int reverse) {
+                           long inner_stride, int ncols, const float2* tw, int width, int rot, hipStream_t st,
+                           int reverse) {
   if (out_d == in || out_p == in || out_d == out_p) return hipErrorInvalidValue;
+  if (rot < 0 || rot >= n) return hipErrorInvalidValue;
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return col_pair_t<N>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, st);
+    return col_pair_t<N>(in, out_p, out_d, n_outer, outer_stride, inner_stride, ncols, tw, width, reverse, rot, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:
@@ -794,11 +859,12 @@ hipError_t launch_col_pair(int n, const float2* in, float2* out_p, float2* out_d
 }
 
 hipError_t launch_xmul_adj(int n, int mode, FieldPtrs in, int nin, float2* out, MulArgs m, const float2* tw,
-                           hipStream_t st) {
+                           int rot, hipStream_t st) {
+  if (rot < 0 || rot >= n) return hipErrorInvalidValue;
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return xmul_adj_t<N>(mode, in, nin, out, m, tw, st);
+    return xmul_adj_t<N>(mode, in, nin, out, m, tw, rot, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:
@@ -807,11 +873,12 @@ hipError_t launch_xmul_adj(int n, int mode, FieldPtrs in, int nin, float2* out, 
 }
 
 hipError_t launch_xmul(int n, int mode, const float2* in, FieldPtrs out, int nout, MulArgs m, const float2* tw,
-                       int width, hipStream_t st) {
+                       int width, int rot, hipStream_t st) {
+  if (rot < 0 || rot >= n) return hipErrorInvalidValue;
   switch (n) {
 #define COLA_CASE(N) \
   case N:            \
-    return xmul_t<N>(mode, in, out, nout, m, tw, width, st);
+    return xmul_t<N>(mode, in, out, nout, m, tw, width, rot, st);
     COLA_FOR_EACH_SIZE(COLA_CASE)
 #undef COLA_CASE
     default:

@@ -129,3 +129,25 @@ def test_density_noalloc_rejects_sizes_beyond_its_scratch():
     with cola.Plan(cola.Config(np=16, nm=32)) as p:
         assert cola.lib().cola_density_noalloc(p._c, None, 1, None) == -1
         assert cola.lib().cola_density_noalloc(None, 1, 1, None) == -1
+
+
+def test_fft_rotation_setting():
+    """Rotated planes: off by default below nm = 1024, on at 1024; the rotation is the x
+    pass's inner DFT length (rows per plane); only -1, 0 and 1 are accepted."""
+    with cola.Plan(cola.Config(np=16, nm=32)) as p:
+        assert p.get_fft_rotation() == 0
+        for bad in (-2, 2, 8):
+            with pytest.raises(cola.ColaError):
+                p.set_fft_rotation(bad)
+        p.set_fft_rotation(1)
+        assert p.get_fft_rotation() == 8
+        p.set_fft_rotation(-1)
+        assert p.get_fft_rotation() == 0
+    with cola.Plan(cola.Config(np=128, nm=768)) as p:
+        assert p.get_fft_rotation() == 0
+        p.set_fft_rotation(1)
+        assert p.get_fft_rotation() == 24
+    with cola.Plan(cola.Config(np=512, nm=1024, box=400.0)) as p:
+        assert p.get_fft_rotation() == 32
+        p.set_fft_rotation(0)
+        assert p.get_fft_rotation() == 0
