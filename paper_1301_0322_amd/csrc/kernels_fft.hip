@@ -274,8 +274,15 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, 
 // inverse transform of i n X (n = m for m <= n/2, else m - n, m the position along
 // the column) and out_p that of X; neither may alias in.  Each tile is read by two
 // blocks, one per output, 8 block indices apart (the same XCD, dispatched together),
-// so the second read is served by that XCD's L2.  in may be a rotated half spectrum
-// (rot, plane index o); the outputs are not rotated.
+// so the second read is served by that XCD's L2.  At n >= 1024 a tile (n rows of B
+// columns, 128 KB) holds one CU's whole LDS budget, 32 tiles fill an XCD's L2 and the
+// partner's read would miss; there one block keeps the tile in registers and writes
+// both outputs (the LDS already limits the pass to two waves per SIMD, which leave
+// room for the second copy).  in may be a rotated half spectrum (rot, plane index o);
+// the outputs are not rotated.
+template <int N>
+constexpr bool col_pair_one_block() { return N >= 1024; }
+
 template <int N, int B>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const float2* __restrict__ in,
                                                                      float2* __restrict__ out_p,
@@ -286,9 +293,13 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const flo
   using P = Pencil<N, B, false>;
   __shared__ __align__(16) float2 ex[P::LDS];
   __shared__ float2 stw[N];
+  constexpr bool ONE = col_pair_one_block<N>();
   long tile;
   int deriv;
-  if (ntiles % kXcdsFft == 0) {
+  if (ONE) {
+    tile = blockIdx.x;
+    deriv = 1;
+  } else if (ntiles % kXcdsFft == 0) {
     const long g = blockIdx.x / (2 * kXcdsFft), w = blockIdx.x % (2 * kXcdsFft);
     tile = g * kXcdsFft + w % kXcdsFft;
     deriv = w < kXcdsFft;
@@ -303,19 +314,33 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const flo
   float2 a[P::R2];
   P::load_a_rows(a, in + origin, [&](int m) { return (long)rot_row<N>(m, (int)o, rot) * inner_stride; });
   load_twiddles(stw, tw, N);
-  if (deriv) {
+  // i n X of A-layout register i2 (position m = i1 + R1 i2)
+  auto times_in = [&](int i2, float2 v) {
     int b, i1;
     P::a_unit(b, i1);
-#pragma unroll
-    for (int i2 = 0; i2 < P::R2; ++i2) {
-      const int m = i1 + P::R1 * i2;
-      a[i2] = mul_si<1>(c_scale(a[i2], (float)(m <= N / 2 ? m : m - N)));
-    }
-  }
-  __syncthreads();
+    const int m = i1 + P::R1 * i2;
+    return mul_si<1>(c_scale(v, (float)(m <= N / 2 ? m : m - N)));
+  };
   float2 q[P::UB][P::R1];
-  P::template fwd_like<1, 1>(a, q, ex, stw);
-  P::store_b(q, (deriv ? out_d : out_p) + origin, inner_stride);
+  if constexpr (ONE) {
+    float2 d[P::R2];
+#pragma unroll
+    for (int i2 = 0; i2 < P::R2; ++i2) d[i2] = times_in(i2, a[i2]);
+    __syncthreads();
+    P::template fwd_like<1, 1>(d, q, ex, stw);
+    P::store_b(q, out_d + origin, inner_stride);
+    __syncthreads();   // the exchange has been read
+    P::template fwd_like<1, 1>(a, q, ex, stw);
+    P::store_b(q, out_p + origin, inner_stride);
+  } else {
+    if (deriv) {
+#pragma unroll
+      for (int i2 = 0; i2 < P::R2; ++i2) a[i2] = times_in(i2, a[i2]);
+    }
+    __syncthreads();
+    P::template fwd_like<1, 1>(a, q, ex, stw);
+    P::store_b(q, (deriv ? out_d : out_p) + origin, inner_stride);
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -584,7 +609,8 @@ static hipError_t col_pair_tb(const float2* in, float2* out_p, float2* out_d, in
     constexpr int T = Pencil<N, B, false>::T;
     const int ntc = ncols / B;
     const long ntiles = (long)n_outer * ntc;
-    hipLaunchKernelGGL((k_col_pair<N, B>), dim3((unsigned)(2 * ntiles)), dim3(T), 0, st, in, out_p, out_d,
+    const long nblocks = col_pair_one_block<N>() ? ntiles : 2 * ntiles;
+    hipLaunchKernelGGL((k_col_pair<N, B>), dim3((unsigned)nblocks), dim3(T), 0, st, in, out_p, out_d,
                        outer_stride, inner_stride, ntc, ntiles, tw, reverse, rot);
     return hipGetLastError();
   } else {
