@@ -84,6 +84,23 @@ __device__ __forceinline__ void load_twiddles(float2* stw, const float2* __restr
   for (int i = threadIdx.x; i < n; i += blockDim.x) stw[i] = tw[i];
 }
 
+// The z passes at n >= 1024 read their twiddles from the global table (8 KB, held in
+// the caches) instead of an LDS copy: their blocks are single waves, and a per-block
+// copy would be a third of the block's LDS and cap a CU at six of them.
+template <int N>
+constexpr bool z_twiddles_global() { return N >= 1024; }
+template <int N>
+constexpr int z_stw_len() { return z_twiddles_global<N>() ? 1 : N; }
+template <int N>
+__device__ __forceinline__ const float2* z_twiddles(float2* stw, const float2* __restrict__ tw) {
+  if constexpr (z_twiddles_global<N>()) {
+    return tw;
+  } else {
+    load_twiddles(stw, tw, N);
+    return stw;
+  }
+}
+
 // ---------------------------------------------------------------------------------
 // z forward: real rows -> half complex rows.
 // X[k] = (Z[k] + conj Z[M-k]) / 2 - i W^k (Z[k] - conj Z[M-k]) / 2, W = exp(-2 pi i / N),
@@ -95,11 +112,11 @@ __global__ __launch_bounds__(ZPencil<N>::T) void k_zfwd(const float* in, float2*
   using P = ZPencil<N>;
   constexpr int M = N / 2;
   __shared__ __align__(16) float2 ex[P::LDS];
-  __shared__ float2 stw[N];
+  __shared__ float2 stw_l[z_stw_len<N>()];
   const long row0 = (long)blockIdx.x * P::NT;
   float2 a[P::R2];
   P::load_a(a, reinterpret_cast<const float2*>(in) + row0 * M, M);
-  load_twiddles(stw, tw, N);
+  const float2* stw = z_twiddles<N>(stw_l, tw);
   __syncthreads();
   float2 q[P::UB][P::R1];
   P::template fwd_like<-1, 2>(a, q, ex, stw);
@@ -155,7 +172,7 @@ __global__ __launch_bounds__(ZPencil<N>::T) void k_zinv(FieldPtrs in, FieldPtrs 
   using P = ZPencil<N>;
   constexpr int M = N / 2;
   __shared__ __align__(16) float2 ex[P::LDS];
-  __shared__ float2 stw[N];
+  __shared__ float2 stw_l[z_stw_len<N>()];
   // the fields' blocks alternate (field fastest), so fields written together by the
   // previous pass are read together
   const int nf = e.nfields;
@@ -164,7 +181,7 @@ __global__ __launch_bounds__(ZPencil<N>::T) void k_zinv(FieldPtrs in, FieldPtrs 
   const long row0 = (e.reverse ? nblk - 1 - blk : blk) * P::NT;
   float2 q[P::UB][P::R1];
   P::load_b(q, in.p[f] + row0 * M, M);
-  load_twiddles(stw, tw, N);
+  const float2* stw = z_twiddles<N>(stw_l, tw);
   if ((e.deriv >> f) & 1) {
     // z derivative: mode k (0 <= k < n/2) times i k, before the Hermitian pairing
 #pragma unroll
@@ -207,8 +224,8 @@ __global__ __launch_bounds__(ZHPencil<N>::T) void k_zinv_hess(FieldPtrs in, floa
   using P = ZHPencil<N>;
   constexpr int M = N / 2;
   __shared__ __align__(16) float2 ex[P::LDS];
-  __shared__ float2 stw[N];
-  load_twiddles(stw, tw, N);
+  __shared__ float2 stw_l[z_stw_len<N>()];
+  const float2* stw = z_twiddles<N>(stw_l, tw);
   const long row0 = (long)blockIdx.x * P::NT;
   // S = xx yy + zz (xx + yy) - xy^2 - yz^2 - zx^2, accumulated as the fields arrive:
   // sum holds xx (+ yy), acc the products.
