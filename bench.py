@@ -566,27 +566,35 @@ def main() -> int:
     plan.trace_enable(0)
     pm_step_ms = steps_rec[0] / steps_rec[1]
 
-    # the same step through the public cola_step call (caller's Lagrangian order,
-    # binned from scratch each call), median over steps 1..n-1
-    plan.init_2lpt(w, p, ws)
-    step_ms = []
-    for i in range(cfg.n_steps):
-        a = torch.cuda.Event(enable_timing=True)
-        b = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        plan.step(i, p, ws)
-        b.record(stream)
-        b.synchronize()
-        if i > 0:
-            step_ms.append(a.elapsed_time(b))
-    api_step_ms = float(np.median(step_ms))
-    # where a public step's time goes: the same calls with every kernel traced
-    plan.init_2lpt(w, p, ws)
-    plan.trace_enable(1)
-    for i in range(cfg.n_steps):
-        plan.step(i, p, ws)
-    api_stages = {k: round(v[0] / cfg.n_steps, 4) for k, v in plan.trace_read().items()}
-    plan.trace_enable(0)
+    # the same step through the public cola_step call, median over steps 1..n-1: plain
+    # (the caller's Lagrangian-order arrays binned and packed from scratch each call)
+    # and with resident steps (each call continues from the sorted state the previous
+    # one left in the workspace)
+    def public_steps(resident):
+        plan.set_resident_steps(resident)
+        plan.init_2lpt(w, p, ws)
+        step_ms = []
+        for i in range(cfg.n_steps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            plan.step(i, p, ws)
+            b.record(stream)
+            b.synchronize()
+            if i > 0:
+                step_ms.append(a.elapsed_time(b))
+        # where a public step's time goes: the same calls with every kernel traced
+        plan.init_2lpt(w, p, ws)
+        plan.trace_enable(1)
+        for i in range(cfg.n_steps):
+            plan.step(i, p, ws)
+        stages_ = {k: round(v[0] / cfg.n_steps, 4) for k, v in plan.trace_read().items()}
+        plan.trace_enable(0)
+        plan.set_resident_steps(0)
+        return float(np.median(step_ms)), stages_
+
+    api_step_ms, api_stages = public_steps(0)
+    res_step_ms, res_stages = public_steps(1)
 
     sb = stage_bytes(np_side, nm)
     per_run = {k: {"ms": ms / args.steps, "launches": n // args.steps, "ms_per_launch": ms / n}
@@ -637,7 +645,15 @@ def main() -> int:
                         "timed": "the public cola_step call on the caller's Lagrangian-order arrays (bins from "
                                  "scratch each call), HIP events around each call, median over steps 1.."
                                  f"{cfg.n_steps - 1} after cola_init_2lpt",
-                        "stages_ms_per_call": api_stages}},
+                        "stages_ms_per_call": api_stages},
+                    "cola_step_call_resident": {
+                        "ms": res_step_ms, "particle_steps_per_s": np_side**3 / (res_step_ms * 1e-3),
+                        "hbm_frac": b_alg / (res_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                        "timed": "the public cola_step call with resident steps on (each call continues from the "
+                                 "tile-sorted state the previous call left in the workspace and writes s, v to the "
+                                 "caller's arrays), HIP events around each call, median over steps 1.."
+                                 f"{cfg.n_steps - 1} after cola_init_2lpt",
+                        "stages_ms_per_call": res_stages}},
         "stages_per_run": per_run,
         "tuning": tuning,
     }

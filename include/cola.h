@@ -175,8 +175,24 @@ int cola_pm_force(cola_plan plan, const float *s, double a, float *acc, void *ws
 /* One COLA step i (0 <= i < n_steps): the kick at a_i (merged half-kicks,
  * eq. KDKALC with a_c = a_i) using the PM force of the current s, then the drift
  * to a_{i+1} with a_c = a_{i+1/2}.  In: s(a_i), v(a_{i-1/2}) (v(a_0) for i = 0).
- * Out, in place: s(a_{i+1}), v(a_{i+1/2}). */
+ * Out, in place: s(a_{i+1}), v(a_{i+1/2}).  With resident steps on
+ * (cola_plan_set_resident_steps), a call that continues the previous resident call
+ * starts from the state that call left in ws. */
 int cola_step(cola_plan plan, int32_t i, const cola_particles *p, void *ws, void *stream);
+
+/* Resident steps (off by default).  With on = 1, cola_step leaves in ws the updated
+ * particle state sorted by mesh tile and its tile bins for the next step (as cola_run
+ * does between its steps), and still writes s and v to the caller's arrays.  The next
+ * cola_step (or cola_finish) of this plan continues from them, skipping the
+ * re-binning and packing of the caller's arrays, when it is called with step index
+ * i + 1 (n_steps for cola_finish), the same particle arrays and the same ws, and no
+ * other call of this library has used ws in between; in every other case it starts
+ * from the caller's arrays as with on = 0.  The caller must not change the particle
+ * arrays (s, v, s1, s2) or ws between such calls: those changes would not be seen.
+ * Results are identical bit for bit either way.  cola_run_checkpointed uses resident
+ * steps internally regardless of this setting.  on = 0 or 1, else COLA_ERR_INVALID.
+ * Host-only. */
+int cola_plan_set_resident_steps(cola_plan plan, int32_t on);
 
 /* Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops).  p->v is updated
  * to v_res(a_n); x_out (device, [3][np^3]) receives the positions (q + s) mod box

@@ -64,6 +64,7 @@ _PROTOS = {
     "cola_plan_set_fft_tile": (ctypes.c_int, [_VP, ctypes.c_int32, ctypes.c_int32]),
     "cola_plan_set_bin_depth": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "cola_plan_set_fft_rotation": (ctypes.c_int, [_VP, ctypes.c_int32]),
+    "cola_plan_set_resident_steps": (ctypes.c_int, [_VP, ctypes.c_int32]),
     "cola_plan_get_fft_rotation": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32)]),
     "cola_plan_get_tuning": (ctypes.c_int, [_VP, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -326,6 +327,12 @@ class Plan:
 
     def set_bin_depth(self, depth: int):
         _check("cola_plan_set_bin_depth", lib().cola_plan_set_bin_depth(self._c, depth))
+
+    def set_resident_steps(self, on: int):
+        """Resident steps: consecutive step() calls on the same particles and workspace keep
+        the tile-sorted state in the workspace (the arrays must not be changed between
+        them).  0 off (default), 1 on."""
+        _check("cola_plan_set_resident_steps", lib().cola_plan_set_resident_steps(self._c, on))
 
     def set_fft_rotation(self, on: int):
         """Rotated planes between the y and x passes of the mesh transforms: 1 on, 0 off,

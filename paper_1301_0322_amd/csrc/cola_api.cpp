@@ -6,8 +6,11 @@
 #include <cmath>
 #include <cstdio>
 #include <string>
+#include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -27,6 +30,19 @@ struct cola_plan_s {
   Bins bins;                      // Eulerian tiles of the force mesh
   int fft_width[2] = {0, 0};      // columns per tile of the mesh-size y passes and x pass (0: default)
   int fft_rot = -1;               // rotate the mesh-size half spectrum between y and x: 1 / 0 (-1: default)
+  // resident steps (cola_plan_set_resident_steps): what the last resident step left in
+  // its workspace, and the workspace generation of the current call
+  int resident = 0;
+  uint64_t ws_gen = 0;
+  struct Resident {
+    bool valid = false;
+    const void* ws = nullptr;
+    const float *s = nullptr, *v = nullptr, *s1 = nullptr, *s2 = nullptr;
+    int next = 0;       // the step index the state is ready for
+    int which = 0;      // sorted workspace copy holding it
+    int parity = 0;     // bin buffers holding its tile counts
+    uint64_t gen = 0;   // workspace generation of the call that left it
+  } res;
   // stage tracing (hipEvent pairs around each launch, on the launch stream)
   int trace = 0;   // trace level: 0 off, 1 every kernel, 2 each cola_run step
   std::vector<hipEvent_t> ev_pool;
@@ -54,13 +70,14 @@ enum Stage : int {
   kStBinCount = 0, kStBinScan, kStBinScatter, kStDeposit, kStZFwd, kStYFwd, kStXPoisson,
   kStYInv, kStZInv, kStGatherKickDrift, kStGatherForce, kStFinish, kStLptZFwd, kStLptYFwd, kStLptX,
   kStLptYInv, kStLptZInv, kStLptHessian, kStNoise, kStFft, kStAdjKick, kStAdjDeposit, kStAdjFft, kStAdjGather,
-  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kStYInvPair, kStAnalysis, kNumStages
+  kStAdjLpt, kStCheckpoint, kStRunStep, kStUnsort, kStYInvPair, kStAnalysis, kStWriteback, kNumStages
 };
 const char* const kStageNames[kNumStages] = {
   "bin_count", "bin_scan", "bin_scatter", "deposit", "fft_z_fwd", "fft_y_fwd",
   "fft_x_poisson", "fft_y_inv", "fft_z_inv", "gather_kick_drift", "gather_force", "gather_finish",
   "lpt_fft_z_fwd", "lpt_fft_y_fwd", "lpt_fft_x_mul", "lpt_fft_y_inv", "lpt_fft_z_inv", "lpt_hessian", "noise",
-  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort", "fft_y_inv_pair", "analysis"};
+  "fft_test", "adj_kick_drift", "adj_deposit", "adj_fft", "adj_gather", "adj_lpt", "checkpoint", "run_step", "unsort",
+  "fft_y_inv_pair", "analysis", "writeback"};
 
 // Trace levels: 1 records an event pair around every kernel launch, 2 only around
 // each whole COLA step of cola_run (stage run_step), so step times carry no
@@ -311,8 +328,20 @@ GatherArgs gather_args(cola_plan p, float* ws) {
   return g;
 }
 
+// Workspace generations: every call that takes a workspace moves that workspace's
+// generation on by one, so a plan can tell whether a workspace still holds what the
+// plan's previous call left there (its generation then moved by exactly this call).
+std::mutex g_ws_mu;
+std::unordered_map<const void*, uint64_t> g_ws_gen;
+
+uint64_t ws_bump(const void* ws) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  return ++g_ws_gen[ws];
+}
+
 int check_common(cola_plan p, const void* ws) {
   if (!p || !ws) return COLA_ERR_INVALID;
+  p->ws_gen = ws_bump(ws);
   return ensure_device(p);
 }
 
@@ -341,14 +370,9 @@ int packed_mesh(cola_plan p, const cola_particles* q, double a, float* ws, hipSt
   return fft_force(p, a, ws, st);
 }
 
-// One COLA step: PM force at a_i, merged kick, drift (eq. KDKALC).  The kick and drift
-// read the packed copy in tile order and write s, v back to the caller's arrays by
-// Lagrangian index; the arithmetic is the cola_run gather's, so both paths agree bit
-// for bit.
-int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st) {
-  const StepRow& row = p->table[i];
-  SortedState pk;
-  COLA_TRY(packed_mesh(p, q, row.a, ws, st, pk));
+// Kick and drift factors of step i (eq. KDKALC) and of the closing half-kick with
+// L+(a_n) (eq. ALCtimestep, Lops).
+KickArgs step_kick(cola_plan p, const StepRow& row) {
   const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
   KickArgs k{};
   k.alpha = (float)row.alpha;
@@ -357,20 +381,10 @@ int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_
   k.beta = (float)row.beta;
   k.dd1 = plain ? 0.0f : (float)row.dd1;
   k.dd2 = plain ? 0.0f : (float)row.dd2;
-  const GatherArgs g = gather_args(p, ws);
-  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
-  return hip_status(traced(p, kStGatherKickDrift, st, [&] {
-    return launch_gather_sorted(lattice(p), p->bins, pk, lagr, bin_buffers(p, ws), kGatherKickDriftLag, g, k, st);
-  }));
+  return k;
 }
 
-// Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops), as the closing step of
-// cola_run: the kick in tile order into the second workspace copy, then back to
-// Lagrangian order with L+ and the positions.
-int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out, float* ws, hipStream_t st) {
-  const StepRow& row = p->table[p->cfg.n_steps];
-  SortedState pk;
-  COLA_TRY(packed_mesh(p, q, row.a, ws, st, pk));
+KickArgs finish_kick(cola_plan p, const StepRow& row) {
   const bool plain = p->cfg.flags & COLA_FLAG_NO_LPT_FRAME;
   KickArgs k{};
   k.alpha = (float)row.alpha;
@@ -379,6 +393,126 @@ int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out
   k.td1 = plain ? 0.0f : (float)row.g.td1;
   k.td2 = plain ? 0.0f : (float)row.g.td2;
   k.box = (float)p->cfg.box;
+  return k;
+}
+
+// One COLA step: PM force at a_i, merged kick, drift (eq. KDKALC).  The kick and drift
+// read the packed copy in tile order and write s, v back to the caller's arrays by
+// Lagrangian index; the arithmetic is the cola_run gather's, so both paths agree bit
+// for bit.
+int step_impl(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st) {
+  p->res.valid = false;
+  const StepRow& row = p->table[i];
+  SortedState pk;
+  COLA_TRY(packed_mesh(p, q, row.a, ws, st, pk));
+  const KickArgs k = step_kick(p, row);
+  const GatherArgs g = gather_args(p, ws);
+  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
+  return hip_status(traced(p, kStGatherKickDrift, st, [&] {
+    return launch_gather_sorted(lattice(p), p->bins, pk, lagr, bin_buffers(p, ws), kGatherKickDriftLag, g, k, st);
+  }));
+}
+
+// Resident steps.  A step that finds in the workspace the tile-sorted state and bins
+// that the previous resident step left there (same particle arrays and workspace, the
+// next step index, and no other call on that workspace since) starts from them as a
+// cola_run step does: scan and scatter of the bins, no re-binning and no packing.
+// Otherwise it bins and packs the caller's arrays.  Its gather writes the next state in
+// this step's tile order, bins it for the next step and writes s and v to the caller's
+// arrays, which are therefore current after every step.
+bool resident_ready(cola_plan p, int i, const cola_particles* q, const float* ws) {
+  const auto& r = p->res;
+  return r.valid && r.ws == ws && r.s == q->s && r.v == q->v && r.s1 == q->s1 && r.s2 == q->s2 && r.next == i &&
+         (r.gen == p->ws_gen || r.gen + 1 == p->ws_gen);
+}
+
+// Deposit from the sorted state src through the bins bb, then the force meshes.
+int sorted_mesh(cola_plan p, const SortedState& src, const BinBuffers& bb, double a, float* ws, hipStream_t st) {
+  const double ratio = (double)lattice(p).ratio;
+  COLA_HIP(traced(p, kStDeposit, st, [&] {
+    return launch_deposit(lattice(p), p->bins, src.s, bb, ws, (float)(ratio * ratio * ratio), st, nullptr, src.lag);
+  }));
+  return fft_force(p, a, ws, st);
+}
+
+// The sorted source of step i and its bins (clear_next: the step's gather bins for the
+// next step); which_dst and parity name the copy and bins the gather writes into.
+int resident_source(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st, bool clear_next,
+                    BinBuffers& bb, SortedState& src, int& which_dst, int& parity) {
+  const Lattice lat = lattice(p);
+  const Bins& b = p->bins;
+  const bool ready = resident_ready(p, i, q, ws);
+  p->res.valid = false;
+  if (ready) {
+    parity = p->res.parity;
+    bb = bin_buffers(p, ws, parity);
+    src = sorted_state(p, ws, p->res.which);
+    which_dst = p->res.which ^ 1;
+    COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, clear_next, st); }));
+    return hip_status(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
+  }
+  parity = 0;
+  bb = bin_buffers(p, ws, 0);
+  src = sorted_state(p, ws, 0);
+  which_dst = 1;
+  const SortedState lagr{q->s, q->v, q->s1, q->s2, nullptr};
+  COLA_HIP(traced(p, kStBinCount, st, [&] { return launch_bin_count(lat, b, q->s, bb, st); }));
+  COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, clear_next, st); }));
+  return hip_status(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter_pack(lat, bb, lagr, src, st); }));
+}
+
+int resident_step(cola_plan p, int i, const cola_particles* q, float* ws, hipStream_t st) {
+  const StepRow& row = p->table[i];
+  BinBuffers bb;
+  SortedState src;
+  int which_dst, parity;
+  COLA_TRY(resident_source(p, i, q, ws, st, true, bb, src, which_dst, parity));
+  COLA_TRY(sorted_mesh(p, src, bb, row.a, ws, st));
+  const KickArgs k = step_kick(p, row);
+  GatherArgs g = gather_args(p, ws);
+  // the slot of every Lagrangian index goes to force mesh 3, free once the forces are
+  // solved, for the write-back of s and v to the caller's arrays in their order
+  g.inv = reinterpret_cast<int*>(ws + 3 * cube(p->cfg.nm));
+  const SortedState dst = sorted_state(p, ws, which_dst);
+  const Lattice lat = lattice(p);
+  COLA_HIP(traced(p, kStGatherKickDrift, st, [&] {
+    return launch_gather_sorted(lat, p->bins, src, dst, bb, kGatherKickDriftInv, g, k, st);
+  }));
+  COLA_HIP(traced(p, kStWriteback, st, [&] { return launch_writeback(lat, dst, g.inv, q->s, q->v, st); }));
+  auto& r = p->res;
+  r.valid = true;
+  r.ws = ws;
+  r.s = q->s;
+  r.v = q->v;
+  r.s1 = q->s1;
+  r.s2 = q->s2;
+  r.next = i + 1;
+  r.which = which_dst;
+  r.parity = parity ^ 1;
+  r.gen = p->ws_gen;
+  return COLA_OK;
+}
+
+// Closing half-kick at a_n and L+(a_n) (eq. ALCtimestep, Lops), as the closing step of
+// cola_run: the kick in tile order into the other workspace copy, then back to
+// Lagrangian order with L+ and the positions.  Starts from the resident state when the
+// last step left one.
+int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out, float* ws, hipStream_t st) {
+  const StepRow& row = p->table[p->cfg.n_steps];
+  BinBuffers bb;
+  SortedState src, out;
+  if (resident_ready(p, p->cfg.n_steps, q, ws)) {
+    int which_dst, parity;
+    COLA_TRY(resident_source(p, p->cfg.n_steps, q, ws, st, false, bb, src, which_dst, parity));
+    COLA_TRY(sorted_mesh(p, src, bb, row.a, ws, st));
+    out = sorted_state(p, ws, which_dst);
+  } else {
+    p->res.valid = false;
+    COLA_TRY(packed_mesh(p, q, row.a, ws, st, src));
+    bb = bin_buffers(p, ws);
+    out = sorted_state(p, ws, 1);
+  }
+  const KickArgs k = finish_kick(p, row);
   GatherArgs g = gather_args(p, ws);
   g.s = q->s;
   g.v = q->v;
@@ -386,10 +520,9 @@ int finish_impl(cola_plan p, const cola_particles* q, float* x_out, float* v_out
   g.s2 = q->s2;
   g.out_a = x_out;
   g.out_b = v_out;
-  const SortedState out = sorted_state(p, ws, 1);
   const Lattice lat = lattice(p);
   COLA_HIP(traced(p, kStFinish, st, [&] {
-    return launch_gather_sorted(lat, p->bins, pk, out, bin_buffers(p, ws), kGatherFinish, g, k, st);
+    return launch_gather_sorted(lat, p->bins, src, out, bb, kGatherFinish, g, k, st);
   }));
   return hip_status(traced(p, kStUnsort, st, [&] { return launch_unsort(lat, out, g, k, st); }));
 }
@@ -694,6 +827,7 @@ int cola_init_2lpt(cola_plan p, const float* w, const cola_particles* q, void* w
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
   if (!w) return COLA_ERR_INVALID;
+  p->res.valid = false;
   hipStream_t st = (hipStream_t)stream;
   const int n = p->cfg.np;
   const long r = cube(n);
@@ -815,7 +949,8 @@ int cola_step(cola_plan p, int32_t i, const cola_particles* q, void* ws_, void* 
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
   if (i < 0 || i >= p->cfg.n_steps) return COLA_ERR_RANGE;
-  return step_impl(p, i, q, static_cast<float*>(ws_), (hipStream_t)stream);
+  float* ws = static_cast<float*>(ws_);
+  return p->resident ? resident_step(p, i, q, ws, (hipStream_t)stream) : step_impl(p, i, q, ws, (hipStream_t)stream);
 }
 
 int cola_finish(cola_plan p, const cola_particles* q, float* x_out, float* v_out, void* ws_, void* stream) {
@@ -902,7 +1037,7 @@ int cola_run_checkpointed(cola_plan p, const float* w, const cola_particles* q, 
     float* dst = ckpt + (size_t)i * 3 * cube(p->cfg.np);
     COLA_HIP(traced(p, kStCheckpoint, st,
                     [&] { return hipMemcpyAsync(dst, q->s, bytes, hipMemcpyDeviceToDevice, st); }));
-    COLA_TRY(step_impl(p, i, q, ws, st));
+    COLA_TRY(resident_step(p, i, q, ws, st));
   }
   float* last = ckpt + (size_t)p->cfg.n_steps * 3 * cube(p->cfg.np);
   COLA_HIP(traced(p, kStCheckpoint, st, [&] { return hipMemcpyAsync(last, q->s, bytes, hipMemcpyDeviceToDevice, st); }));
@@ -966,6 +1101,14 @@ int cola_plan_set_bin_depth(cola_plan p, int32_t tz) {
   if (!p || (tz != 8 && tz != 16 && tz != 32 && tz != 64)) return COLA_ERR_INVALID;
   if (p->cfg.nm % tz) return COLA_ERR_UNSUPPORTED_SIZE;
   p->bins = make_bins(p->cfg.nm, tz);
+  p->res.valid = false;
+  return COLA_OK;
+}
+
+int cola_plan_set_resident_steps(cola_plan p, int32_t on) {
+  if (!p || (on != 0 && on != 1)) return COLA_ERR_INVALID;
+  p->resident = on;
+  p->res.valid = false;
   return COLA_OK;
 }
 
@@ -1002,6 +1145,7 @@ int cola_autotune(cola_plan p, const cola_particles* q, void* ws_, size_t ws_byt
                   const char* cache_path, int32_t* used_cache) {
   COLA_TRY(check_common(p, ws_));
   COLA_TRY(check_particles(q));
+  p->res.valid = false;
   if (used_cache) *used_cache = 0;
   hipStream_t st = (hipStream_t)stream;
   int dev = 0;
@@ -1105,6 +1249,7 @@ struct cola_ensemble_s {
   hipGraphExec_t exec = nullptr;
   int device = -1;
   int members = 0;
+  std::vector<const void*> ws;   // member workspaces (each replay writes them)
 };
 
 int cola_ensemble_create(int32_t n, const cola_plan* plans, const float* const* w, const cola_particles* parts,
@@ -1152,6 +1297,7 @@ int cola_ensemble_create(int32_t n, const cola_plan* plans, const float* const* 
   if (rc == COLA_OK) {
     e->graph = graph;
     e->members = n;
+    e->ws.assign(ws, ws + n);
     (void)hipGetDevice(&e->device);
     rc = hip_status(hipGraphInstantiate(&e->exec, graph, nullptr, nullptr, 0));
   }
@@ -1175,6 +1321,7 @@ int cola_ensemble_create(int32_t n, const cola_plan* plans, const float* const* 
 
 int cola_ensemble_launch(cola_ensemble e, void* stream) {
   if (!e || !e->exec) return COLA_ERR_INVALID;
+  for (const void* w : e->ws) ws_bump(w);
   return hip_status(hipGraphLaunch(e->exec, (hipStream_t)stream));
 }
 

@@ -190,6 +190,8 @@ enum GatherMode : int {
   kGatherFinish = 2,        // the kick only, written packed for launch_unsort (x, L+)
   kGatherKickDriftLag = 3,  // kick and drift, s and v written to the caller's Lagrangian-order arrays
                             // (dst SoA, by each record's Lagrangian index; no binning)
+  kGatherKickDriftInv = 4,  // kGatherKickDrift, and a.inv[Lagrangian index] = dst slot (for
+                            // launch_writeback)
 };
 struct GatherArgs {
   const float* g0;
@@ -201,6 +203,7 @@ struct GatherArgs {
   const float* s2;
   float* out_a;     // force gather: acc; launch_unsort: x
   float* out_b;     // launch_unsort: v_phys
+  int* inv;         // kGatherKickDriftInv: slot of every Lagrangian index ([n])
 };
 // Force gather (cola_pm_force): a.out_a[d n + p] = F_d of particle p of the SoA
 // displacements a.s, through the tile lists of bb.
@@ -227,9 +230,14 @@ hipError_t launch_bin_scatter_pack(Lattice lat, BinBuffers bb, SortedState src, 
 // (ordered by this step's tiles) and bins it for the next step (bb.count_next,
 // bb.key_rank by dst slot); kGatherFinish writes s and the kicked v of list position
 // j as float4 j of dst.s (s.x s.y s.z v.x) and float2 j of dst.s + 4n (v.y v.z), and
-// sets dst.lag[Lagrangian index] = j, for launch_unsort.
+// sets dst.lag[Lagrangian index] = j, for launch_unsort.  kGatherKickDriftBoth does
+// what kGatherKickDrift does and also records each record's dst slot in a.inv at its
+// Lagrangian index.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st);
+// The caller's Lagrangian-order s and v ([3][n]) from the packed state w (a
+// kGatherKickDriftInv dst) and its inverse permutation inv.
+hipError_t launch_writeback(Lattice lat, SortedState w, const int* inv, float* s, float* v, hipStream_t st);
 // Lagrangian order from a kGatherFinish output w: a.s, a.v take s and v; a.out_a
 // x = (q + s) mod L (k.box); a.out_b v_phys = v + k.td1 a.s1 + k.td2 a.s2, the L+ of
 // the closing step (a.s1, a.s2 the caller's arrays).

@@ -837,8 +837,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
       for (int d = 0; d < 3; ++d) {
         const float a1 = r.s1[d], a2 = r.s2[d];
         const float v = r.v[d] + k.alpha * (f[d] - k.t2d1 * a1 - k.t2d2 * a2);
-        if constexpr (MODE == kGatherKickDrift || MODE == kGatherKickDriftLag)
-          snew[d] = r.s[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
+        if constexpr (MODE != kGatherFinish) snew[d] = r.s[d] + k.beta * v + k.dd1 * a1 + k.dd2 * a2;
         vf[d] = v;
       }
       if constexpr (MODE == kGatherKickDriftLag) {
@@ -850,7 +849,8 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
           dst.v[d * n + r.lag] = vf[d];
         }
       }
-      if constexpr (MODE == kGatherKickDrift) {
+      if constexpr (MODE == kGatherKickDriftInv) g.inv[r.lag] = j;
+      if constexpr (MODE == kGatherKickDrift || MODE == kGatherKickDriftInv) {
         float4* q = reinterpret_cast<float4*>(dst.s);
         q[j] = make_float4(snew[0], snew[1], snew[2], vf[0]);
         q[n + j] = make_float4(vf[1], vf[2], r.s1[0], r.s1[1]);
@@ -866,7 +866,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_gather_sorted(Lattice lat,
         dst.lag[r.lag] = j;
       }
     }
-    if constexpr (MODE == kGatherKickDrift) {
+    if constexpr (MODE == kGatherKickDrift || MODE == kGatherKickDriftInv) {
       int bin = 0;
       if (in) bin = key_of<TZ>(bins, stencil_of(lat, r.lag, snew).c);
       const int rank = wave_rank(in, bin, count_next);
@@ -1060,6 +1060,9 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
   if (mode == kGatherKickDrift)
     hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDrift>), grid, block, 0, st, lat, b, src, dst, bb.idx,
                        bb.offset, bb.heavy, a, k, bb.key_rank, bb.count_next);
+  else if (mode == kGatherKickDriftInv)
+    hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDriftInv>), grid, block, 0, st, lat, b, src, dst, bb.idx,
+                       bb.offset, bb.heavy, a, k, bb.key_rank, bb.count_next);
   else if (mode == kGatherKickDriftLag)
     hipLaunchKernelGGL((k_gather_sorted<TZ, kGatherKickDriftLag>), grid, block, 0, st, lat, b, src, dst, bb.idx,
                        bb.offset, bb.heavy, a, k, bb.key_rank, bb.count_next);
@@ -1070,7 +1073,10 @@ static void gather_sorted_tz(Lattice lat, Bins b, SortedState src, SortedState d
 
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
                                 GatherArgs a, KickArgs k, hipStream_t st) {
-  if (mode != kGatherKickDrift && mode != kGatherFinish && mode != kGatherKickDriftLag) return hipErrorInvalidValue;
+  if (mode != kGatherKickDrift && mode != kGatherFinish && mode != kGatherKickDriftLag &&
+      mode != kGatherKickDriftInv)
+    return hipErrorInvalidValue;
+  if (mode == kGatherKickDriftInv && !a.inv) return hipErrorInvalidValue;
   if (mode == kGatherKickDriftLag) {
     // dst is the caller's SoA arrays (s, v) in Lagrangian order
     if (!dst.s || !dst.v || dst.lag) return hipErrorInvalidValue;
@@ -1090,19 +1096,49 @@ hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedStat
 // covers a 4 x 4 x 16 block of the Lagrangian grid (when np allows), whose particles
 // sit in a few neighbouring tiles, so its scattered reads stay local; its writes are
 // runs of 16 consecutive elements.
-__global__ __launch_bounds__(kPartThreads) void k_unsort(Lattice lat, SortedState w, GatherArgs g, KickArgs k) {
+// Lagrangian index of this thread in the unsort-order walks: a block takes a 4 x 4 x 16
+// block of the Lagrangian grid (when np allows), whose particles sit in a few
+// neighbouring tiles, so its out-of-order reads stay local and its writes are runs of
+// 16 consecutive elements.
+__device__ __forceinline__ long unsort_index(const Lattice& lat) {
   const int np = lat.np;
-  const long n = lat.npart;
-  long p;
   if (np % 16 == 0) {
     const int nbk = np / 16, nbj = np / 4;
     const int b = blockIdx.x;
     const int bk = b % nbk, bj = (b / nbk) % nbj, bi = b / (nbk * nbj);
     const int t = threadIdx.x;
-    p = ((long)(4 * bi + t / 64) * np + 4 * bj + (t / 16) % 4) * np + 16 * bk + t % 16;
-  } else {
-    p = (long)blockIdx.x * kPartThreads + threadIdx.x;
+    return ((long)(4 * bi + t / 64) * np + 4 * bj + (t / 16) % 4) * np + 16 * bk + t % 16;
   }
+  return (long)blockIdx.x * kPartThreads + threadIdx.x;
+}
+
+__global__ __launch_bounds__(kPartThreads) void k_writeback(Lattice lat, const float4* __restrict__ w,
+                                                            const int* __restrict__ inv, float* __restrict__ s,
+                                                            float* __restrict__ v) {
+  const long n = lat.npart;
+  const long p = unsort_index(lat);
+  if (p >= n) return;
+  const long j = inv[p];
+  const float4 a = w[j], b = w[n + j];   // (s.x s.y s.z v.x), (v.y v.z s1.x s1.y)
+  s[p] = a.x;
+  s[n + p] = a.y;
+  s[2 * n + p] = a.z;
+  v[p] = a.w;
+  v[n + p] = b.x;
+  v[2 * n + p] = b.y;
+}
+
+hipError_t launch_writeback(Lattice lat, SortedState w, const int* inv, float* s, float* v, hipStream_t st) {
+  if (!w.s || !inv || !s || !v || reinterpret_cast<uintptr_t>(w.s) % 16 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_writeback, dim3(part_blocks(lat.npart)), dim3(kPartThreads), 0, st, lat,
+                     reinterpret_cast<const float4*>(w.s), inv, s, v);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kPartThreads) void k_unsort(Lattice lat, SortedState w, GatherArgs g, KickArgs k) {
+  const int np = lat.np;
+  const long n = lat.npart;
+  const long p = unsort_index(lat);
   if (p >= n) return;
   const long j = w.lag[p];
   const float4 a = reinterpret_cast<const float4*>(w.s)[j];

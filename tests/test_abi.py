@@ -151,3 +151,12 @@ def test_fft_rotation_setting():
         assert p.get_fft_rotation() == 32
         p.set_fft_rotation(0)
         assert p.get_fft_rotation() == 0
+
+
+def test_resident_steps_setting():
+    with cola.Plan(cola.Config(np=16, nm=32)) as p:
+        p.set_resident_steps(1)
+        p.set_resident_steps(0)
+        for bad in (-1, 2):
+            with pytest.raises(cola.ColaError):
+                p.set_resident_steps(bad)

@@ -1,0 +1,194 @@
+"""Resident steps: consecutive cola_step calls continue from the tile-sorted state and
+bins that the previous call left in the workspace, as cola_run's steps do.
+
+Every result must equal cola_run's and the plain per-step path's bit for bit (the
+deposit sums 64-bit fixed point and the gathers share their arithmetic), and any other
+use of the workspace, a step out of sequence or a different particle set in between
+must make the next step start again from the caller's arrays.
+"""
+import pytest
+import torch
+
+import paper_1301_0322_amd as cola
+from paper_1301_0322_amd import inputs
+from tests.gpu_util import announce, dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+_PM = cola.COLA_FLAG_NO_LPT_FRAME
+_LOG = cola.COLA_FLAG_LOG_A_STEPS
+
+
+def _empty3(n):
+    return torch.empty((3, n**3), dtype=torch.float32, device="cuda")
+
+
+def _run(plan, cfg, w, ws):
+    p = cola.Particles.empty(cfg.np)
+    x, v = _empty3(cfg.np), _empty3(cfg.np)
+    plan.run(w, p, x, v, ws)
+    return x, v, p
+
+
+def _steps(plan, cfg, w, ws, order=None, between=None):
+    """init_2lpt, the steps in `order` (default 0..n-1) with between(i) after step i,
+    then finish."""
+    p = cola.Particles.empty(cfg.np)
+    plan.init_2lpt(w, p, ws)
+    for i in (range(cfg.n_steps) if order is None else order):
+        plan.step(i, p, ws)
+        if between is not None:
+            between(i, p)
+    x, v = _empty3(cfg.np), _empty3(cfg.np)
+    plan.finish(p, x, v, ws)
+    return x, v, p
+
+
+def _same(a, b):
+    """Which of x, v_phys, s, v agree bit for bit (else their rel L2 difference)."""
+    out = {}
+    for name, s, t in zip(("x", "v_phys", "s", "v"), (a[0], a[1], a[2].s, a[2].v), (b[0], b[1], b[2].s, b[2].v)):
+        out[name] = bool(torch.equal(s, t)) or rel_l2(host(t), host(s))
+    return out
+
+
+def _identical(a, b):
+    d = _same(a, b)
+    return all(val is True for val in d.values()), d
+
+
+@pytest.mark.parametrize("np_side,nm,flags", [(16, 32, 0), (32, 64, 0), (32, 64, _PM | _LOG), (64, 128, 0)])
+def test_resident_steps_equal_run(np_side, nm, flags):
+    announce(f"resident steps np={np_side} nm={nm} flags={flags}")
+    cfg = cola.Config(np=np_side, nm=nm, flags=flags)
+    w = dev(inputs.white_noise(np_side, 7))
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        ref = _run(plan, cfg, w, ws)
+        plain = _steps(plan, cfg, w, ws)
+        plan.set_resident_steps(1)
+        res = _steps(plan, cfg, w, ws)
+        torch.cuda.synchronize()
+    ok, d = _identical(ref, plain)
+    assert ok, d
+    ok, d = _identical(ref, res)
+    assert ok, d
+
+
+def test_resident_steps_full_size_equal_run():
+    """256^3 particles on the 512^3 mesh, seed 1302."""
+    announce("resident steps 256/512")
+    cfg = cola.Config(np=256, nm=512)
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        w = torch.empty(256**3, dtype=torch.float32, device="cuda")
+        plan.noise(1302, w)
+        ref = _run(plan, cfg, w, ws)
+        plan.set_resident_steps(1)
+        res = _steps(plan, cfg, w, ws)
+        torch.cuda.synchronize()
+        same = _same(ref, res)
+        del ws, w, ref, res
+        torch.cuda.empty_cache()
+    assert all(val is True for val in same.values()), same
+
+
+def test_resident_state_is_rebuilt_after_other_calls():
+    """A density and a force evaluation on the same workspace between steps overwrite
+    the bins and meshes; the following steps must start again from the arrays."""
+    announce("resident steps with calls in between")
+    cfg = cola.Config(np=32, nm=64)
+    w = dev(inputs.white_noise(32, 8))
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        ref = _run(plan, cfg, w, ws)
+        plan.set_resident_steps(1)
+        rho = torch.empty(64**3, dtype=torch.float32, device="cuda")
+        acc = _empty3(32)
+
+        def between(i, p):
+            if i == 2:
+                plan.density(p.s, rho, ws)
+            if i == 5:
+                plan.pm_force(p.s, 0.5, acc, ws)
+        res = _steps(plan, cfg, w, ws, between=between)
+        torch.cuda.synchronize()
+    assert float(rho.double().sum()) == pytest.approx(64**3, rel=1e-5)
+    ok, d = _identical(ref, res)
+    assert ok, d
+
+
+def test_resident_step_out_of_sequence():
+    """Repeating step 1 applies it to the advanced arrays, as the plain path does."""
+    announce("resident steps out of sequence")
+    cfg = cola.Config(np=32, nm=64)
+    w = dev(inputs.white_noise(32, 9))
+    order = [0, 1, 1] + list(range(2, cfg.n_steps))
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        plain = _steps(plan, cfg, w, ws, order=order)
+        plan.set_resident_steps(1)
+        res = _steps(plan, cfg, w, ws, order=order)
+        torch.cuda.synchronize()
+    ok, d = _identical(plain, res)
+    assert ok, d
+
+
+def test_resident_steps_two_particle_sets_one_workspace():
+    """Two realizations stepped alternately through one plan and one workspace: each
+    step sees the other set's call in between and starts from its own arrays."""
+    announce("resident steps two particle sets")
+    cfg = cola.Config(np=32, nm=64)
+    wa, wb = dev(inputs.white_noise(32, 10)), dev(inputs.white_noise(32, 11))
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        ref_a, ref_b = _run(plan, cfg, wa, ws), _run(plan, cfg, wb, ws)
+        plan.set_resident_steps(1)
+        pa, pb = cola.Particles.empty(32), cola.Particles.empty(32)
+        plan.init_2lpt(wa, pa, ws)
+        plan.init_2lpt(wb, pb, ws)
+        for i in range(cfg.n_steps):
+            plan.step(i, pa, ws)
+            plan.step(i, pb, ws)
+        out = []
+        for p in (pa, pb):
+            x, v = _empty3(32), _empty3(32)
+            plan.finish(p, x, v, ws)
+            out.append((x, v, p))
+        torch.cuda.synchronize()
+    ok, d = _identical(ref_a, out[0])
+    assert ok, d
+    ok, d = _identical(ref_b, out[1])
+    assert ok, d
+
+
+def test_checkpointed_run_equals_run():
+    """cola_run_checkpointed steps through resident steps; its output and its last
+    checkpoint (s at a_n) equal cola_run's."""
+    announce("checkpointed run 32/64")
+    cfg = cola.Config(np=32, nm=64)
+    w = dev(inputs.white_noise(32, 12))
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        ref = _run(plan, cfg, w, ws)
+        p = cola.Particles.empty(32)
+        x, v = _empty3(32), _empty3(32)
+        ckpt = torch.empty((cfg.n_steps + 1, 3, 32**3), dtype=torch.float32, device="cuda")
+        plan.run_checkpointed(w, p, x, v, ckpt, ws)
+        steps = _steps(plan, cfg, w, ws)
+        torch.cuda.synchronize()
+    ok, d = _identical(ref, (x, v, p))
+    assert ok, d
+    assert torch.equal(ckpt[cfg.n_steps], ref[2].s)
+    assert torch.equal(ckpt[0], cola_init_s(cfg, w))
+    ok, d = _identical(ref, steps)
+    assert ok, d
+
+
+def cola_init_s(cfg, w):
+    with cola.Plan(cfg) as plan:
+        p = cola.Particles.empty(cfg.np)
+        plan.init_2lpt(w, p, plan.workspace())
+        torch.cuda.synchronize()
+        return p.s.clone()
+
