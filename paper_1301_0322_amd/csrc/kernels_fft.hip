@@ -291,14 +291,14 @@ __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col(FieldPtrs in, 
 // inverse transform of i n X (n = m for m <= n/2, else m - n, m the position along
 // the column) and out_p that of X; neither may alias in.  Each tile is read by two
 // blocks, one per output, 8 block indices apart (the same XCD, dispatched together),
-// so the second read is served by that XCD's L2.  At n >= 1024 a tile (n rows of B
-// columns, 128 KB) holds one CU's whole LDS budget, 32 tiles fill an XCD's L2 and the
-// partner's read would miss; there one block keeps the tile in registers and writes
-// both outputs (the LDS already limits the pass to two waves per SIMD, which leave
-// room for the second copy).  in may be a rotated half spectrum (rot, plane index o);
-// the outputs are not rotated.
+// so the second read is served by that XCD's L2.  At n >= 768 a tile (n rows of B
+// columns, 96 or 128 KB) takes a CU's whole LDS budget for its exchange, 32 of them
+// fill an XCD's L2 and the partner's read would miss; there one block keeps the tile
+// in registers and writes both outputs (the LDS already limits the pass to two waves
+// per SIMD, which leave room for the second copy).  in may be a rotated half spectrum
+// (rot, plane index o); the outputs are not rotated.
 template <int N>
-constexpr bool col_pair_one_block() { return N >= 1024; }
+constexpr bool col_pair_one_block() { return N >= 768; }
 
 template <int N, int B>
 __global__ __launch_bounds__((Pencil<N, B, false>::T)) void k_col_pair(const float2* __restrict__ in,
