@@ -487,6 +487,8 @@ def main() -> int:
     ap.add_argument("--rocprof-pmc", metavar="DIR", help="print the summary of a rocprofv3 --pmc run and exit")
     ap.add_argument("--rocprof-busy", metavar="DIR",
                     help="print the GPU-busy fraction of each launch window of a rocprofv3 kernel trace and exit")
+    ap.add_argument("--busy-gap-us", type=float, default=2000.0,
+                    help="with --rocprof-busy: idle gap (us) that separates launch windows")
     ap.add_argument("--rocprof-hbm", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print HBM bytes per dispatch from a FETCH_SIZE and a WRITE_SIZE run and exit")
     ap.add_argument("--stage", default="", help="with --rocprof-hbm: the key: value block of this stage")
@@ -497,7 +499,7 @@ def main() -> int:
         print(rocprof_hbm_summary(*args.rocprof_hbm, stage=args.stage))
         return 0
     if args.rocprof_busy:
-        print(rocprof_busy_summary(args.rocprof_busy))
+        print(rocprof_busy_summary(args.rocprof_busy, gap_us=args.busy_gap_us))
         return 0
     if args.rocprof_trace:
         print(rocprof_trace_summary(args.rocprof_trace))
