@@ -610,12 +610,19 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
     }
   }
   __syncthreads();
+  // every cell written once, four consecutive z cells per 16-byte store (lo[2] and
+  // nm are multiples of 8, so each run of four is aligned)
+  static_assert(TZ % 4 == 0, "16-byte row pieces");
   const long nm = lat.nm;
-  for (int i = threadIdx.x; i < D::CORE; i += D::TT) {
+  for (int i = 4 * threadIdx.x; i < D::CORE; i += 4 * D::TT) {
     const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
     const long cell = ((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z;
 #pragma unroll
-    for (int c = 0; c < NW; ++c) rho[c * nm * nm * nm + cell] = tile_value(tile[c * D::CORE + i]);
+    for (int c = 0; c < NW; ++c) {
+      const ACC* v = tile + c * D::CORE + i;
+      *reinterpret_cast<float4*>(rho + c * nm * nm * nm + cell) =
+          make_float4(tile_value(v[0]), tile_value(v[1]), tile_value(v[2]), tile_value(v[3]));
+    }
   }
 }
 
