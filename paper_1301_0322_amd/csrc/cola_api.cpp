@@ -365,7 +365,7 @@ int packed_mesh(cola_plan p, const cola_particles* q, double a, float* ws, hipSt
   COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, false, st); }));
   COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter_pack(lat, bb, lagr, pk, st); }));
   COLA_HIP(traced(p, kStDeposit, st, [&] {
-    return launch_deposit(lat, b, pk.s, bb, ws, (float)(ratio * ratio * ratio), st, nullptr, pk.lag);
+    return launch_deposit(lat, b, pk.s, bb, ws, (float)(ratio * ratio * ratio), st, pk.lag);
   }));
   return fft_force(p, a, ws, st);
 }
@@ -430,7 +430,7 @@ bool resident_ready(cola_plan p, int i, const cola_particles* q, const float* ws
 int sorted_mesh(cola_plan p, const SortedState& src, const BinBuffers& bb, double a, float* ws, hipStream_t st) {
   const double ratio = (double)lattice(p).ratio;
   COLA_HIP(traced(p, kStDeposit, st, [&] {
-    return launch_deposit(lattice(p), p->bins, src.s, bb, ws, (float)(ratio * ratio * ratio), st, nullptr, src.lag);
+    return launch_deposit(lattice(p), p->bins, src.s, bb, ws, (float)(ratio * ratio * ratio), st, src.lag);
   }));
   return fft_force(p, a, ws, st);
 }
@@ -540,6 +540,7 @@ struct AdjLayout {
   float* lam_s1;
   float* lam_s2;
   float* lpt;       // 10 np^3
+  unsigned* wmax;   // four words: max |weight| of the weighted deposit
   size_t bytes;
 };
 
@@ -555,7 +556,8 @@ AdjLayout adj_layout(cola_plan p, float* ws) {
   L.lam_s1 = q ? q + 6 * n : nullptr;
   L.lam_s2 = q ? q + 9 * n : nullptr;
   L.lpt = q ? q + 12 * n : nullptr;
-  L.bytes = head + (3 * (size_t)r + 22 * (size_t)n) * sizeof(float);
+  L.wmax = q ? reinterpret_cast<unsigned*>(q + 22 * n) : nullptr;
+  L.bytes = head + (3 * (size_t)r + 22 * (size_t)n + 4) * sizeof(float);
   return L;
 }
 
@@ -630,7 +632,7 @@ int run_adjoint(cola_plan p, const float* w, const float* ckpt, const float* dL_
     const BinBuffers bb = bin_buffers(p, ws);
     // the three components in one particle walk (amesh[d] = amesh[0] + d nm^3)
     COLA_HIP(traced(p, kStAdjDeposit, st, [&] {
-      return launch_deposit3(lat, b, s_i, bb, L.amesh[0], mass, L.lam_v, st);
+      return launch_deposit3(lat, b, s_i, bb, L.amesh[0], mass, L.lam_v, L.wmax, st);
     }));
     // rbar = sum_d K_d^T nu_d (conjugate multiplier), into amesh[0]
     const float2* tw = p->d_tw_nm;
@@ -990,7 +992,7 @@ int cola_run(cola_plan p, const float* w, const cola_particles* q, float* x_out,
     COLA_HIP(traced(p, kStBinScan, st, [&] { return launch_bin_scan(b, bb, !last, st); }));
     COLA_HIP(traced(p, kStBinScatter, st, [&] { return launch_bin_scatter(lat, bb, st); }));
     COLA_HIP(traced(p, kStDeposit, st,
-                    [&] { return launch_deposit(lat, b, src.s, bb, ws, mass, st, nullptr, src.lag); }));
+                    [&] { return launch_deposit(lat, b, src.s, bb, ws, mass, st, src.lag); }));
     COLA_TRY(fft_force(p, row.a, ws, st));
     KickArgs k{};
     k.alpha = (float)row.alpha;

@@ -169,11 +169,13 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st);
 // [3][np^3] in Lagrangian order.  weight (optional, [np^3] by Lagrangian index): the
 // particle carries mass * weight.
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                          hipStream_t st, const float* weight = nullptr, const int* lag = nullptr);
+                          hipStream_t st, const int* lag = nullptr);
 // Three weighted deposits in one particle walk: rho + c nm^3 receives the CIC deposit
-// of mass * weight[c n + Lagrangian index], c = 0..2 (s SoA in Lagrangian order).
+// of mass * weight[c n + Lagrangian index], c = 0..2 (s SoA in Lagrangian order), summed
+// in 64-bit fixed point after scaling by a power of two from max |weight| (computed into
+// wmax, four words of device scratch).  Deterministic: independent of particle order.
 hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                           const float* weight, hipStream_t st);
+                           const float* weight, unsigned* wmax, hipStream_t st);
 
 struct KickArgs {
   float alpha;                 // kick factor

@@ -66,23 +66,22 @@ struct TileDims {
   static constexpr int TT = TZ >= 64 ? 512 : kPartThreads;
 };
 
-// Deposit accumulators.  A tile sums its CIC contributions in LDS either as FP32
-// (float atomics) or as 64-bit fixed point with 32 fraction bits (integer atomics).
-// Integer adds are exact and associative, so the fixed-point sum does not depend on
-// the order of the adds; each contribution is its FP32 value rounded to 2^-32, and
-// the tile value is rounded to FP32 once.  It is also the faster form on gfx950,
-// whose LDS integer atomics run far ahead of its LDS float atomics.  The range is
-// enough for any supported size: a cell holds at most the total mass nm^3 <= 2^30.
+// Deposit accumulators: a tile sums its CIC contributions in LDS as 64-bit fixed point
+// with 32 fraction bits (two's complement, integer atomics).  Integer adds are exact
+// and associative, so the sum does not depend on the order of the adds; each
+// contribution is its FP32 value rounded to 2^-32, and the tile value is rounded to
+// FP32 once.  It is also the faster form on gfx950, whose LDS integer atomics run far
+// ahead of its LDS float atomics.  The range is enough for any mass deposit (a cell
+// holds at most the total mass nm^3 <= 2^30); weighted deposits scale their weights
+// into range first (k_deposit_tiles).
 constexpr float kFixScale = 4294967296.f;   // 2^32
-__device__ __forceinline__ void tile_add(float* p, float x) { atomicAdd(p, x); }
-// x >= 0 (a mass share): round(x 2^32) from the exact split x = h + r, h = floor(x),
-// as h 2^32 + rint(r 2^32); r 2^32 < 2^32 - 2^8 for a float r < 1.
+// |x| < 2^31: round(x 2^32) from the exact split x = h + r, h = floor(x), r in [0, 1),
+// as h 2^32 + rint(r 2^32); r 2^32 <= 2^32 - 2^8 for a float r < 1.
 __device__ __forceinline__ void tile_add(unsigned long long* p, float x) {
   const float h = floorf(x);
   const unsigned lo = (unsigned)rintf((x - h) * kFixScale);
-  atomicAdd(p, ((unsigned long long)(unsigned)h << 32) | lo);
+  atomicAdd(p, ((unsigned long long)(long long)(int)h << 32) | lo);
 }
-__device__ __forceinline__ float tile_value(float v) { return v; }
 __device__ __forceinline__ float tile_value(unsigned long long v) { return (float)(long long)v * (1.f / kFixScale); }
 
 // Base cell (wrapped) and CIC fraction along one axis.  t = s nm / L - 1/2 with nm / L
@@ -467,8 +466,8 @@ __device__ __forceinline__ float corner_value(const float* tile_field, const flo
 // local coordinate in its own tile, minus the tile extent when it comes from the
 // lower neighbour along d; its stencil corners inside tile t are added to the LDS
 // tile (accumulator ACC as above) and the tile's cells are then stored.
-//   ACC = unsigned long long: fixed-point sums (mass deposits); float: FP32 atomics
-//   (weighted deposits, whose weights have no bounded scale).
+//   ACC = unsigned long long: fixed-point sums (the only accumulator: mass deposits,
+//   and weighted ones scaled by the power of two that wmax gives).
 // idx holds slots of s; with lag (optional) s is a packed state (positions in the
 // first float4 of each slot) and lag maps a slot to its Lagrangian index; without,
 // s is SoA [3][np^3] in Lagrangian order.  weight is indexed by Lagrangian index.
@@ -482,10 +481,23 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
                                                                 const int* __restrict__ idx,
                                                                 const int* __restrict__ offset,
                                                                 const int* __restrict__ heavy, float* __restrict__ rho,
-                                                                float mass, const float* __restrict__ weight) {
+                                                                float mass, const float* __restrict__ weight,
+                                                                const unsigned* __restrict__ wmax) {
   using D = TileDims<TZ>;
   static_assert(NW == 1 || NW == 3, "one or three weight planes");
   __shared__ ACC tile[NW * D::CORE];
+  // Weighted fixed-point deposits (wmax = bits of max |weight|): the weights are scaled
+  // by a power of two 2^k chosen so that no cell's sum, at most npart mass max|weight|
+  // in magnitude, can leave the 31 integer bits of the accumulator, and the cells are
+  // scaled back by 2^-k (both exact).  Mass deposits keep k = 0.
+  float wscale = 1.f, winv = 1.f;
+  if (wmax) {
+    int e = 0;
+    (void)frexp((double)mass * (double)__uint_as_float(*wmax) * (double)lat.npart, &e);
+    const int k = min(max(30 - e, -120), 120);
+    wscale = ldexpf(1.f, k);
+    winv = ldexpf(1.f, -k);
+  }
   __shared__ int rbeg[kDepRanges], rpre[kDepRanges + 1], rmask[kDepRanges];
   TileGeom g;
   bool listed;
@@ -589,7 +601,7 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
       const int rz = (int)((unsigned)st.c[2] % TZ) - ((msk[u] & 4) ? TZ : 0);
       float mw[NW];
 #pragma unroll
-      for (int c = 0; c < NW; ++c) mw[c] = weight ? mass * weight[c * lat.npart + lg[u]] : mass;
+      for (int c = 0; c < NW; ++c) mw[c] = weight ? mass * weight[c * lat.npart + lg[u]] * wscale : mass;
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
         const int x = rx + a;
@@ -620,8 +632,8 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
 #pragma unroll
     for (int c = 0; c < NW; ++c) {
       const ACC* v = tile + c * D::CORE + i;
-      *reinterpret_cast<float4*>(rho + c * nm * nm * nm + cell) =
-          make_float4(tile_value(v[0]), tile_value(v[1]), tile_value(v[2]), tile_value(v[3]));
+      *reinterpret_cast<float4*>(rho + c * nm * nm * nm + cell) = make_float4(
+          tile_value(v[0]) * winv, tile_value(v[1]) * winv, tile_value(v[2]) * winv, tile_value(v[3]) * winv);
     }
   }
 }
@@ -1033,24 +1045,36 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Largest |x| over count floats, as the bits of a non-negative float in *out (atomicMax
+// on the bit patterns, which order non-negative floats); *out is cleared first.
+__global__ __launch_bounds__(kPartThreads) void k_absmax(const float* __restrict__ x, long count,
+                                                         unsigned* __restrict__ out) {
+  float m = 0.f;
+  for (long i = (long)blockIdx.x * kPartThreads + threadIdx.x; i < count; i += (long)gridDim.x * kPartThreads)
+    m = fmaxf(m, fabsf(x[i]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if (__lane_id() == 0) atomicMax(out, __float_as_uint(m));
+}
+
 hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                           const float* weight, hipStream_t st) {
-  if (!weight) return hipErrorInvalidValue;
-  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float, 3>), dim3(tile_blocks(b)),
+                           const float* weight, unsigned* wmax, hipStream_t st) {
+  if (!weight || !wmax) return hipErrorInvalidValue;
+  // the scale of the fixed-point sums: max |weight| over the three components
+  const hipError_t e = launch_fill(reinterpret_cast<float*>(wmax), 4, 0.0f, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(kPartThreads), 0, st, weight, 3 * lat.npart, wmax);
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long, 3>), dim3(tile_blocks(b)),
                                             dim3(TileDims<TZ>::TT), 0, st, lat, b, s, nullptr, bb.idx, bb.offset,
-                                            bb.heavy, rho, mass, weight))
+                                            bb.heavy, rho, mass, weight, wmax))
   return hipGetLastError();
 }
 
 hipError_t launch_deposit(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
-                          hipStream_t st, const float* weight, const int* lag) {
-  if (weight)
-    COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, float>), dim3(tile_blocks(b)), dim3(TileDims<TZ>::TT),
-                                              0, st, lat, b, s, lag, bb.idx, bb.offset, bb.heavy, rho, mass, weight))
-  else
-    COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long>), dim3(tile_blocks(b)),
-                                              dim3(TileDims<TZ>::TT), 0, st, lat, b, s, lag, bb.idx, bb.offset, bb.heavy, rho, mass,
-                                              weight))
+                          hipStream_t st, const int* lag) {
+  COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long>), dim3(tile_blocks(b)),
+                                            dim3(TileDims<TZ>::TT), 0, st, lat, b, s, lag, bb.idx, bb.offset, bb.heavy, rho,
+                                            mass, nullptr, nullptr))
   return hipGetLastError();
 }
 

@@ -179,6 +179,20 @@ def test_adjoint_full_size_against_the_oracle():
     assert np.all(err <= bar), list(zip(proj, fd, traj))
 
 
+def test_adjoint_is_deterministic():
+    """The adjoint's weighted deposits sum 64-bit fixed point scaled by a power of two
+    taken from max |weight|, so two gradients of the same loss agree bit for bit."""
+    announce("adjoint determinism 32/64")
+    cfg = cola.Config(np=32, nm=64)
+    w = inputs.white_noise(32, 13)
+    target = inputs.white_noise(64, 14).reshape(64, 64, 64).astype(np.float64) * 0.1 + 1.0
+    g1, l1, r1 = _gpu_grad(cfg, w, target)
+    g2, l2, r2 = _gpu_grad(cfg, w, target)
+    assert np.array_equal(r1, r2) and l1 == l2
+    assert np.array_equal(g1, g2)
+    assert np.abs(g1).max() > 0
+
+
 def test_adjoint_full_size_directional_derivative():
     """128^3 particles / 256^3 mesh: the adjoint's directional derivative against a
     central difference of the GPU forward itself (FP32, so a loose bar)."""
