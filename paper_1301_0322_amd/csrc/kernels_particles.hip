@@ -11,6 +11,8 @@
 // Tile blocks are remapped so that each of the 8 XCDs (which receive blocks
 // round-robin) works on one contiguous slab of tiles and shares its L2 with the
 // neighbouring tiles whose halo rows it reads.
+#include <type_traits>
+
 #include "internal.hpp"
 
 
@@ -560,8 +562,11 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
   const int total = rpre[kDepRanges];
   // particles per lane per batch: a tile's particles plus its neighbours' boundary
   // classes (about 1.3 per tile thread on average) fit one or two batches, and more
-  // slots per lane only add predicated-off work
-  constexpr int U = 1;
+  // slots per lane only add predicated-off work.  A crowded tile (listed) walks tens of
+  // thousands of particles in one block; four per lane keep four record loads in
+  // flight per batch on that block's long serial loop.
+  auto walk = [&](auto slots) {
+  constexpr int U = decltype(slots)::value;
   for (int base = 0; base < total; base += U * D::TT) {   // block-uniform trip count
     float sv[U][3];
     unsigned lg[U];
@@ -621,6 +626,11 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
       }
     }
   }
+  };
+  if (listed)   // block-uniform
+    walk(std::integral_constant<int, 4>{});
+  else
+    walk(std::integral_constant<int, 1>{});
   __syncthreads();
   // every cell written once, four consecutive z cells per 16-byte store (lo[2] and
   // nm are multiples of 8, so each run of four is aligned)
