@@ -228,6 +228,9 @@ int cola_adjoint_workspace_bytes(cola_plan plan, size_t *bytes);
  * transposes); then the transpose of the 2LPT initial conditions, where the
  * second-order source is quadratic in the Hessian of the linear potential.
  * The final half-kick does not move particles and does not enter.
+ * Deterministic: the weighted deposits scale their weights by a power of two taken
+ * from max |weight| (so that no cell sum can leave the range) and sum 64-bit fixed
+ * point; a non-finite dL_drho or intermediate cotangent makes dL_dw NaN.
  * ws: at least cola_adjoint_workspace_bytes() bytes (not shared with a running
  * forward call). */
 int cola_run_adjoint(cola_plan plan, const float *w, const float *ckpt, const float *dL_drho, float *dL_dw, void *ws,
@@ -255,7 +258,7 @@ int cola_plan_set_fft_tile(cola_plan plan, int32_t pass, int32_t width);
  * particles are binned for the deposit and gather (a tuning knob; results are
  * identical for every depth: the mass deposit sums 64-bit fixed point and a
  * particle's arithmetic does not depend on its tile; the adjoint's weighted deposits
- * sum FP32 and agree up to summation order).  COLA_ERR_INVALID for other depths,
+ * sum the same fixed point after an exact power-of-two scaling).  COLA_ERR_INVALID for other depths,
  * COLA_ERR_UNSUPPORTED_SIZE when depth does not divide nm.  Call
  * cola_workspace_bytes again afterwards.  Host-only. */
 int cola_plan_set_bin_depth(cola_plan plan, int32_t depth);

@@ -492,13 +492,20 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
   // by a power of two 2^k chosen so that no cell's sum, at most npart mass max|weight|
   // in magnitude, can leave the 31 integer bits of the accumulator, and the cells are
   // scaled back by 2^-k (both exact).  Mass deposits keep k = 0.
+  // A non-finite weight (max |weight| inf or NaN) has no such scale: every cell of the
+  // output is then NaN, as an FP32 sum would have carried it.
   float wscale = 1.f, winv = 1.f;
   if (wmax) {
-    int e = 0;
-    (void)frexp((double)mass * (double)__uint_as_float(*wmax) * (double)lat.npart, &e);
-    const int k = min(max(30 - e, -120), 120);
-    wscale = ldexpf(1.f, k);
-    winv = ldexpf(1.f, -k);
+    const float wm = __uint_as_float(*wmax);
+    if (wm <= __FLT_MAX__) {
+      int e = 0;
+      (void)frexp((double)mass * (double)wm * (double)lat.npart, &e);
+      const int k = min(max(30 - e, -120), 120);
+      wscale = ldexpf(1.f, k);
+      winv = ldexpf(1.f, -k);
+    } else {
+      winv = __int_as_float(0x7fc00000);
+    }
   }
   __shared__ int rbeg[kDepRanges], rpre[kDepRanges + 1], rmask[kDepRanges];
   TileGeom g;
@@ -1057,14 +1064,17 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 
 // Largest |x| over count floats, as the bits of a non-negative float in *out (atomicMax
 // on the bit patterns, which order non-negative floats); *out is cleared first.
+// max |x| as the bits of a non-negative float, whose unsigned order is the numeric
+// order with +inf above every finite value and NaN above +inf: a non-finite entry
+// gives a non-finite maximum.
 __global__ __launch_bounds__(kPartThreads) void k_absmax(const float* __restrict__ x, long count,
                                                          unsigned* __restrict__ out) {
-  float m = 0.f;
+  unsigned m = 0;
   for (long i = (long)blockIdx.x * kPartThreads + threadIdx.x; i < count; i += (long)gridDim.x * kPartThreads)
-    m = fmaxf(m, fabsf(x[i]));
+    m = max(m, __float_as_uint(x[i]) & 0x7fffffffu);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-  if (__lane_id() == 0) atomicMax(out, __float_as_uint(m));
+  for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
+  if (__lane_id() == 0) atomicMax(out, m);
 }
 
 hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,

@@ -193,6 +193,50 @@ def test_adjoint_is_deterministic():
     assert np.abs(g1).max() > 0
 
 
+def _adjoint(plan, cfg, w, g_rho):
+    ws = plan.workspace()
+    p = cola.Particles.empty(cfg.np)
+    ckpt = torch.empty((cfg.n_steps + 1, 3, cfg.np**3), dtype=torch.float32, device="cuda")
+    x = torch.empty((3, cfg.np**3), dtype=torch.float32, device="cuda")
+    v = torch.empty_like(x)
+    plan.run_checkpointed(w, p, x, v, ckpt, ws)
+    g = torch.empty_like(w)
+    plan.run_adjoint(w, ckpt, g_rho, g, plan.adjoint_workspace())
+    torch.cuda.synchronize()
+    return host(g)
+
+
+def test_adjoint_bin_depths_give_identical_gradients():
+    """The weighted deposits sum fixed point, so the tile depth (which block adds which
+    particle, and the crowded-tile list) leaves the gradient unchanged bit for bit."""
+    cfg = cola.Config(np=32, nm=64)
+    w = dev(inputs.white_noise(32, 15))
+    g_rho = dev(np.random.default_rng(6).standard_normal(64**3).astype(np.float32))
+    grads = []
+    with cola.Plan(cfg) as plan:
+        for depth in (8, 16, 32, 64):
+            announce(f"adjoint 32/64 depth {depth}")
+            plan.set_bin_depth(depth)
+            grads.append(_adjoint(plan, cfg, w, g_rho))
+    for k in range(1, 4):
+        assert np.array_equal(grads[k], grads[0]), (k, rel_l2(grads[k], grads[0]))
+    assert np.abs(grads[0]).max() > 0
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_adjoint_nonfinite_cotangent_gives_nan(bad):
+    """A non-finite dL/drho has no fixed-point scale: the gradient comes out NaN
+    instead of silently finite."""
+    announce(f"adjoint non-finite cotangent {bad}")
+    cfg = cola.Config(np=16, nm=32)
+    w = dev(inputs.white_noise(16, 16))
+    g_rho = np.random.default_rng(7).standard_normal(32**3).astype(np.float32)
+    g_rho[1234] = bad
+    with cola.Plan(cfg) as plan:
+        g = _adjoint(plan, cfg, w, dev(g_rho))
+    assert np.isnan(g).all()
+
+
 def test_adjoint_full_size_directional_derivative():
     """128^3 particles / 256^3 mesh: the adjoint's directional derivative against a
     central difference of the GPU forward itself (FP32, so a loose bar)."""
