@@ -34,6 +34,11 @@
  * - ws is the caller-owned device workspace of at least cola_workspace_bytes()
  *   bytes, 256-byte aligned.  Calls that share a workspace must be ordered on one
  *   stream.
+ * - A plan is not thread-safe: calls on one plan must not overlap in time (they
+ *   update its resident-step record and trace buffers).  Different plans may be
+ *   used from different threads.  The library keeps a process-wide count per
+ *   workspace address (a few bytes each, never freed) to tell whether a workspace
+ *   still holds what a plan's previous call left there.
  * - Status: 0 on success, a negative COLA_ERR_* code otherwise; no exception or
  *   abort crosses this ABI.  cola_strerror() describes a code; after COLA_ERR_HIP,
  *   cola_last_hip_error() returns the hipError_t of the calling thread.
