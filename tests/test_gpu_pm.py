@@ -76,6 +76,51 @@ def test_unperturbed_lattice_feels_no_force():
         assert host(acc.abs().max()) < 1e-6
 
 
+def _collapsed(np_side, nm, x0):
+    """Displacements that put every particle at the point x0, in a box of nm unit cells
+    (Lagrangian points q = i box/np; s = x0 - q, exact in FP32 for these sizes)."""
+    q = np.arange(np_side) * (nm / np_side)
+    qx, qy, qz = np.meshgrid(q, q, q, indexing="ij")
+    return np.stack([x0[0] - qx, x0[1] - qy, x0[2] - qz]).reshape(3, -1).astype(np.float32)
+
+
+def _point_density(nm, total, x0):
+    """CIC of a single point mass on unit cells centred at c + 1/2 (the deposit's
+    definition with all the mass in one particle)."""
+    rho = np.zeros((nm, nm, nm))
+    t = np.asarray(x0, dtype=np.float64) - 0.5
+    c = np.floor(t).astype(int)
+    f = t - c
+    for a in (0, 1):
+        for b in (0, 1):
+            for e in (0, 1):
+                w = (f[0] if a else 1 - f[0]) * (f[1] if b else 1 - f[1]) * (f[2] if e else 1 - f[2])
+                rho[(c[0] + a) % nm, (c[1] + b) % nm, (c[2] + e) % nm] += total * w
+    return rho
+
+
+@pytest.mark.parametrize("np_side,nm", [(32, 64), (128, 256), (256, 512)])
+def test_density_of_all_particles_at_one_point(np_side, nm):
+    """The degenerate deposit: every particle in one cell of one tile (the whole particle
+    set on the crowded-tile list, every LDS add on the same four cells).  The CIC
+    fractions 1/4, 3/4 and 0 make each share and each sum exact, so the density must
+    equal the point-mass closed form exactly: four cells holding nm^3 times 3/16, 9/16,
+    1/16 and 3/16, every other cell zero."""
+    announce(f"density all particles at one point np={np_side} nm={nm}")
+    x0 = (10.75, 20.25, 30.5)
+    s = _collapsed(np_side, nm, x0)
+    with cola.Plan(cola.Config(np=np_side, nm=nm, box=float(nm))) as plan:
+        ws = plan.workspace()
+        rho = torch.empty(nm**3, dtype=torch.float32, device="cuda")
+        plan.density(dev(s), rho, ws)
+        got = host(rho).reshape(nm, nm, nm)
+        del ws, rho
+        torch.cuda.empty_cache()
+    ref = _point_density(nm, float(nm) ** 3, x0)
+    assert np.count_nonzero(ref) == 4
+    assert np.array_equal(got, ref.astype(np.float32)), (np.argwhere(got != ref)[:4], got[got != ref][:4])
+
+
 def test_density_full_size_matches_oracle():
     """256^3 particles on the 512^3 mesh in the benchmarked launch configuration
     (bin depth 32), every cell against the oracle's FP64 deposit, same bar as the

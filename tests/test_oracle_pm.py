@@ -52,6 +52,20 @@ def test_single_particle_stencils():
     assert rho[2, 0, 0].item() == pytest.approx(0.25, abs=1e-15)
 
 
+def test_all_particles_at_one_point_deposit_as_one_particle():
+    """Displacements s = x0 - q carry every lattice point to x0 (some across the
+    periodic box): the deposit must equal that of one particle holding all the mass."""
+    n_p, n_m, box = 8, 16, 16.0
+    x0 = [3.25, 12.75, 0.5]
+    q = torch.arange(n_p, dtype=F64) * (box / n_p)
+    qx, qy, qz = torch.meshgrid(q, q, q, indexing="ij")
+    s = torch.stack([x0[0] - qx, x0[1] - qy, x0[2] - qz])
+    rho = pm.cic_deposit(s, n_p, n_m, box)
+    one = pm.cic_deposit_points(torch.tensor(x0, dtype=F64).view(3, 1), n_m, box, mass=float(n_m**3))
+    assert torch.allclose(rho, one, rtol=0, atol=1e-9)
+    assert int((one != 0).sum()) == 4   # z fraction 0: four cells
+
+
 @pytest.mark.parametrize("ratio", [1, 2])
 def test_unperturbed_lattice_is_uniform_and_force_free(ratio):
     n_p, box = 8, 40.0
