@@ -193,7 +193,9 @@ int cola_step(cola_plan plan, int32_t i, const cola_particles *p, void *ws, void
  * i + 1 (n_steps for cola_finish), the same particle arrays and the same ws, and no
  * other call of this library has used ws in between; in every other case it starts
  * from the caller's arrays as with on = 0.  The caller must not change the particle
- * arrays (s, v, s1, s2) or ws between such calls: those changes would not be seen.
+ * arrays (s, v, s1, s2) or ws between such calls: those changes would not be seen
+ * (to change them, or to pass a new ws at the same address, call this function
+ * again first: any call drops the record, so the next step starts from the arrays).
  * Results are identical bit for bit either way.  cola_run_checkpointed uses resident
  * steps internally regardless of this setting.  on = 0 or 1, else COLA_ERR_INVALID.
  * Host-only. */
