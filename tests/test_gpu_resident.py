@@ -192,3 +192,32 @@ def cola_init_s(cfg, w):
         torch.cuda.synchronize()
         return p.s.clone()
 
+
+def test_setting_resident_steps_again_drops_the_record():
+    """A change to the particle arrays between resident calls is not seen (the next
+    call continues from the workspace state), unless cola_plan_set_resident_steps is
+    called again first, which makes the next step start from the arrays."""
+    announce("resident steps record dropped by the setter")
+    cfg = cola.Config(np=32, nm=64)
+    w = dev(inputs.white_noise(32, 17))
+
+    def perturb(i, p):
+        if i == 4:
+            p.s.add_(0.01)
+
+    with cola.Plan(cfg) as plan:
+        ws = plan.workspace()
+        plain = _steps(plan, cfg, w, ws, between=perturb)
+        plan.set_resident_steps(1)
+
+        def perturb_and_drop(i, p):
+            perturb(i, p)
+            if i == 4:
+                plan.set_resident_steps(1)
+        dropped = _steps(plan, cfg, w, ws, between=perturb_and_drop)
+        kept = _steps(plan, cfg, w, ws, between=perturb)
+        torch.cuda.synchronize()
+    ok, d = _identical(plain, dropped)
+    assert ok, d
+    ok, d = _identical(plain, kept)
+    assert not ok, "the perturbation should not be seen while the record is kept"
