@@ -317,6 +317,15 @@ int cola_ensemble_create(int32_t n, const cola_plan *plans, const float *const *
                          float *const *x_out, float *const *v_out, void *const *ws, cola_ensemble *out);
 /* Runs every member once: a single graph launch on stream. */
 int cola_ensemble_launch(cola_ensemble ens, void *stream);
+/* One-shot batched run of an ensemble of realizations (Section 4: ensembles of
+ * mock catalogues as the method's use): the members and buffers as in
+ * cola_ensemble_create, captured into one graph, launched once on stream and freed.
+ * Unlike the other calls that take a stream, it waits for that launch before it
+ * returns (the graph must outlive it).  Each member's x_out, v_out and particles
+ * equal those of cola_run bit for bit.  To run the same members again, create the
+ * ensemble once and launch it. */
+int cola_run_batched(int32_t n, const cola_plan *plans, const float *const *w, const cola_particles *p,
+                     float *const *x_out, float *const *v_out, void *const *ws, void *stream);
 /* Frees the graph (the caller synchronises any launch first).  NULL is accepted. */
 int cola_ensemble_destroy(cola_ensemble ens);
 

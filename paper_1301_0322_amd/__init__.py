@@ -74,6 +74,9 @@ _PROTOS = {
     "cola_ensemble_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
                                             ctypes.POINTER(ColaParticles), ctypes.POINTER(_VP),
                                             ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP)]),
+    "cola_run_batched": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                        ctypes.POINTER(ColaParticles), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
+                                        ctypes.POINTER(_VP), _VP]),
     "cola_ensemble_launch": (ctypes.c_int, [_VP, _VP]),
     "cola_ensemble_destroy": (ctypes.c_int, [_VP]),
     "cola_trace_enable": (ctypes.c_int, [_VP, ctypes.c_int]),
@@ -462,6 +465,28 @@ class Ensemble:
             self.close()
         except Exception:
             pass
+
+
+def run_batched(plans, noises, particles, xs, vs, workspaces, stream=None):
+    """cola_run_batched: whole runs of several plans as one graph launch, waited for.
+    Every buffer is the caller's and is checked against its plan's sizes first."""
+    plans = list(plans)
+    n = len(plans)
+    lists = [list(noises), list(particles), list(xs), list(vs), list(workspaces)]
+    if n == 0 or any(len(l) != n for l in lists):
+        raise ValueError("run_batched needs one noise, particle set, x, v and workspace per plan")
+    noises, particles, xs, vs, workspaces = lists
+    for k, pl in enumerate(plans):
+        _need(noises[k], 4 * pl.cfg.np**3, f"noises[{k}]")
+        particles[k].checked(pl.cfg.np)
+        _need(xs[k], 12 * pl.cfg.np**3, f"xs[{k}]")
+        _need(vs[k], 12 * pl.cfg.np**3, f"vs[{k}]")
+        _need(workspaces[k], pl.workspace_bytes(), f"workspaces[{k}]")
+    arr = lambda vals: (_VP * n)(*vals)
+    parts = (ColaParticles * n)(*[p.to_c() for p in particles])
+    _check("cola_run_batched", lib().cola_run_batched(
+        n, arr([pl._c for pl in plans]), arr([_ptr(w) for w in noises]), parts, arr([_ptr(x) for x in xs]),
+        arr([_ptr(v) for v in vs]), arr([_ptr(w) for w in workspaces]), _stream(stream)))
 
 
 def run(cfg: Config, w, device="cuda"):

@@ -1321,6 +1321,17 @@ int cola_ensemble_create(int32_t n, const cola_plan* plans, const float* const* 
   return COLA_OK;
 }
 
+int cola_run_batched(int32_t n, const cola_plan* plans, const float* const* w, const cola_particles* parts,
+                     float* const* x_out, float* const* v_out, void* const* ws, void* stream) {
+  cola_ensemble e = nullptr;
+  COLA_TRY(cola_ensemble_create(n, plans, w, parts, x_out, v_out, ws, &e));
+  int rc = cola_ensemble_launch(e, stream);
+  // the graph is freed only after its launch has finished
+  if (rc == COLA_OK) rc = hip_status(hipStreamSynchronize((hipStream_t)stream));
+  const int rc_destroy = cola_ensemble_destroy(e);
+  return rc != COLA_OK ? rc : rc_destroy;
+}
+
 int cola_ensemble_launch(cola_ensemble e, void* stream) {
   if (!e || !e->exec) return COLA_ERR_INVALID;
   for (const void* w : e->ws) ws_bump(w);

@@ -132,3 +132,36 @@ def test_ensemble_rejects_a_short_noise():
     finally:
         for p in plans:
             p.close()
+
+
+def test_run_batched_equals_individual_runs():
+    """cola_run_batched (one capture, one launch, waited for) gives every member the
+    same x, v and particle state as its own cola_run, bit for bit, for uneven sizes."""
+    announce("run_batched vs cola_run")
+    cfgs = [cola.Config(np=n, nm=m) for n, m, _ in MEMBERS]
+    plans = [cola.Plan(c) for c in cfgs]
+    try:
+        noises = [dev(inputs.white_noise(n, seed)) for n, _, seed in MEMBERS]
+        ref = []
+        for pl, c, w in zip(plans, cfgs, noises):
+            p = cola.Particles.empty(c.np)
+            x = torch.empty((3, c.np**3), dtype=torch.float32, device="cuda")
+            v = torch.empty_like(x)
+            pl.run(w, p, x, v, pl.workspace())
+            ref.append((x, v, p))
+        parts = [cola.Particles.empty(c.np) for c in cfgs]
+        xs = [torch.empty((3, c.np**3), dtype=torch.float32, device="cuda") for c in cfgs]
+        vs = [torch.empty_like(x) for x in xs]
+        wss = [pl.workspace() for pl in plans]
+        cola.run_batched(plans, noises, parts, xs, vs, wss)
+        for k, (x, v, p) in enumerate(ref):
+            assert torch.equal(xs[k], x), k
+            assert torch.equal(vs[k], v), k
+            assert torch.equal(parts[k].s, p.s) and torch.equal(parts[k].v, p.v), k
+        with pytest.raises(ValueError, match="one noise"):
+            cola.run_batched(plans, noises[:-1], parts, xs, vs, wss)
+        with pytest.raises(ValueError, match="workspaces\\[0\\]"):
+            cola.run_batched(plans, noises, parts, xs, vs, [torch.empty(16, device="cuda")] + wss[1:])
+    finally:
+        for pl in plans:
+            pl.close()
