@@ -232,7 +232,7 @@ hipError_t launch_bin_scatter_pack(Lattice lat, BinBuffers bb, SortedState src, 
 // (ordered by this step's tiles) and bins it for the next step (bb.count_next,
 // bb.key_rank by dst slot); kGatherFinish writes s and the kicked v of list position
 // j as float4 j of dst.s (s.x s.y s.z v.x) and float2 j of dst.s + 4n (v.y v.z), and
-// sets dst.lag[Lagrangian index] = j, for launch_unsort.  kGatherKickDriftBoth does
+// sets dst.lag[Lagrangian index] = j, for launch_unsort.  kGatherKickDriftInv does
 // what kGatherKickDrift does and also records each record's dst slot in a.inv at its
 // Lagrangian index.
 hipError_t launch_gather_sorted(Lattice lat, Bins b, SortedState src, SortedState dst, BinBuffers bb, int mode,
