@@ -1062,11 +1062,9 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Largest |x| over count floats, as the bits of a non-negative float in *out (atomicMax
-// on the bit patterns, which order non-negative floats); *out is cleared first.
-// max |x| as the bits of a non-negative float, whose unsigned order is the numeric
-// order with +inf above every finite value and NaN above +inf: a non-finite entry
-// gives a non-finite maximum.
+// max |x| over count floats into *out (which the caller clears), as the bits of a
+// non-negative float, whose unsigned order is the numeric order with +inf above every
+// finite value and NaN above +inf: a non-finite entry gives a non-finite maximum.
 __global__ __launch_bounds__(kPartThreads) void k_absmax(const float* __restrict__ x, long count,
                                                          unsigned* __restrict__ out) {
   unsigned m = 0;
