@@ -468,13 +468,14 @@ def bench_adjoint(stream) -> dict:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c1", choices=sorted(CONFIGS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ensemble", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--gpus", type=int, default=1, help="GPUs (this build runs on one; N > 1 exits with a message)")
+    ap.add_argument("--steps", type=int, default=5, help="timed bench steps (one step = one whole cola_run)")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed cola_runs before the timed ones")
+    ap.add_argument("--config", default="c1", choices=sorted(CONFIGS),
+                    help="workload of the headline line (default c1: 256^3 particles, 512^3 mesh)")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the FP64 oracle on the host")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 48-member ensemble figures")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 128^3 / 256^3 forward + adjoint figures")
     ap.add_argument("--autotune", action="store_true",
                     help="time the FFT tile widths and bin depth on the IC state first and keep the fastest "
                          "(default: the plan's defaults, the configuration the committed profiles cover)")
