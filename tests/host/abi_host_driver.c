@@ -56,6 +56,37 @@ int main(void) {
   c = base(32, 64); c.flags = 0x100; if (cola_plan_create(&c, &p) == COLA_OK) bad++;
   if (cola_plan_create(NULL, &p) == COLA_OK) bad++;
   if (cola_plan_destroy(NULL) != COLA_OK) bad++;
+  /* error paths of the device entry points with null arguments: each must return an
+     error status (on a machine without a GPU, possibly COLA_ERR_HIP) without touching
+     memory */
+  {
+    cola_config cc = base(16, 32);
+    cola_plan q = NULL;
+    if (cola_plan_create(&cc, &q) != COLA_OK) bad++;
+    cola_particles none = {NULL, NULL, NULL, NULL};
+    size_t sz = 0;
+    double dd[8];
+    int32_t li[64];
+    if (cola_step(NULL, 0, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_step(q, 0, &none, NULL, NULL) == COLA_OK) bad++;
+    if (cola_step(q, 99, &none, NULL, NULL) == COLA_OK) bad++;
+    if (cola_run(q, NULL, &none, NULL, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_finish(q, &none, NULL, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_density(q, NULL, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_density_noalloc(q, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_pm_force(q, NULL, 0.5, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_cross_power(q, NULL, NULL, dd, NULL, NULL) == COLA_OK) bad++;
+    if (cola_fft_r2c(q, 17, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_run_adjoint(q, NULL, NULL, NULL, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_ensemble_create(0, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_run_batched(0, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == COLA_OK) bad++;
+    if (cola_ensemble_launch(NULL, NULL) == COLA_OK) bad++;
+    if (cola_ensemble_destroy(NULL) != COLA_OK) bad++;
+    if (cola_autotune(q, &none, NULL, 0, NULL, NULL, li) == COLA_OK) bad++;
+    if (cola_trace_read(q, dd, li, 1) == COLA_OK) bad++;   /* capacity below the stage count */
+    if (cola_workspace_bytes(NULL, &sz) == COLA_OK) bad++;
+    if (cola_plan_destroy(q) != COLA_OK) bad++;
+  }
   for (int s = -10; s <= 1; ++s) if (!cola_strerror(s)) bad++;
   for (int k = -1; k <= cola_trace_stage_count(); ++k) (void)cola_trace_stage_name(k);
   printf(bad ? "FAIL %d\n" : "OK\n", bad);
