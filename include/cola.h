@@ -299,7 +299,9 @@ int cola_plan_get_tuning(cola_plan plan, int32_t *y_width, int32_t *x_width, int
  * ws_bytes bytes (cola_tuning_workspace_bytes() lets every depth be tried; depths
  * whose binning buffers would not fit are skipped).  Call cola_workspace_bytes
  * again afterwards.  This call synchronises stream.
- * Results of the tuned plan agree with the default up to FP32 rounding. */
+ * Results of the tuned plan equal the default's bit for bit: no tuning knob changes
+ * the arithmetic (tile widths set how many columns a block transforms, the bin depth
+ * which block adds a particle into fixed-point sums). */
 int cola_autotune(cola_plan plan, const cola_particles *p, void *ws, size_t ws_bytes, void *stream,
                   const char *cache_path, int32_t *used_cache);
 /* Workspace bytes that let cola_autotune try every tile depth. */
