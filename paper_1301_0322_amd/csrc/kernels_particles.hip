@@ -71,8 +71,9 @@ struct TileDims {
 // Deposit accumulators: a tile sums its CIC contributions in LDS as 64-bit fixed point
 // with 32 fraction bits (two's complement, integer atomics).  Integer adds are exact
 // and associative, so the sum does not depend on the order of the adds; each
-// contribution is its FP32 value rounded to 2^-32, and the tile value is rounded to
-// FP32 once.  It is also the faster form on gfx950, whose LDS integer atomics run far
+// contribution is its FP32 value rounded to 2^-32, and the tile value is converted to
+// FP32 within one ulp (tile_value).  It is also the faster form on gfx950, whose LDS
+// integer atomics run far
 // ahead of its LDS float atomics.  The range is enough for any mass deposit (a cell
 // holds at most the total mass nm^3 <= 2^30); weighted deposits scale their weights
 // into range first (k_deposit_tiles).
@@ -84,7 +85,14 @@ __device__ __forceinline__ void tile_add(unsigned long long* p, float x) {
   const unsigned lo = (unsigned)rintf((x - h) * kFixScale);
   atomicAdd(p, ((unsigned long long)(long long)(int)h << 32) | lo);
 }
-__device__ __forceinline__ float tile_value(unsigned long long v) { return (float)(long long)v * (1.f / kFixScale); }
+// The cell value v 2^-32 of a sum v = hi 2^32 + lo (hi signed, lo unsigned) as
+// hi + lo 2^-32 in one fused multiply-add: lo converts exactly below 2^24 and with a
+// relative error of 2^-24 above, hi exactly below 2^24, so the result is within one
+// ulp of the correctly rounded value (exact when hi = 0), in three instructions where
+// a correctly rounded conversion of the 64-bit integer takes about fourteen.
+__device__ __forceinline__ float tile_value(unsigned long long v) {
+  return fmaf((float)(unsigned)v, 1.f / kFixScale, (float)(int)(v >> 32));
+}
 
 // Base cell (wrapped) and CIC fraction along one axis.  t = s nm / L - 1/2 with nm / L
 // carried as the float pair inv_dx + inv_dx_lo: a single float nm / L is off by up to
@@ -641,16 +649,26 @@ __global__ __launch_bounds__(TileDims<TZ>::TT) void k_deposit_tiles(Lattice lat,
   __syncthreads();
   // every cell written once, four consecutive z cells per 16-byte store (lo[2] and
   // nm are multiples of 8, so each run of four is aligned)
+  // A thread's runs are 4 TT cells apart, a whole number of x planes of the tile, so its
+  // output address advances by a fixed stride.
   static_assert(TZ % 4 == 0, "16-byte row pieces");
+  static_assert((4 * D::TT) % (TZ * kTY) == 0, "runs a whole number of x planes apart");
   const long nm = lat.nm;
-  for (int i = 4 * threadIdx.x; i < D::CORE; i += 4 * D::TT) {
-    const int z = i % TZ, y = (i / TZ) % kTY, x = i / (TZ * kTY);
-    const long cell = ((g.lo[0] + x) * nm + g.lo[1] + y) * nm + g.lo[2] + z;
+  const int i0 = 4 * threadIdx.x;
+  float* out = rho + ((g.lo[0] + i0 / (TZ * kTY)) * nm + g.lo[1] + (i0 / TZ) % kTY) * nm + g.lo[2] + i0 % TZ;
+  const long stride = (long)(4 * D::TT / (TZ * kTY)) * nm * nm;
+  for (int i = i0; i < D::CORE; i += 4 * D::TT, out += stride) {
 #pragma unroll
     for (int c = 0; c < NW; ++c) {
       const ACC* v = tile + c * D::CORE + i;
-      *reinterpret_cast<float4*>(rho + c * nm * nm * nm + cell) = make_float4(
-          tile_value(v[0]) * winv, tile_value(v[1]) * winv, tile_value(v[2]) * winv, tile_value(v[3]) * winv);
+      float4 f = make_float4(tile_value(v[0]), tile_value(v[1]), tile_value(v[2]), tile_value(v[3]));
+      if (wmax) {   // weighted: undo the power-of-two scale (NaN if no scale existed)
+        f.x *= winv;
+        f.y *= winv;
+        f.z *= winv;
+        f.w *= winv;
+      }
+      *reinterpret_cast<float4*>(out + c * nm * nm * nm) = f;
     }
   }
 }

@@ -2,8 +2,8 @@
 
 Tolerances (derived from FP32 arithmetic): CIC weights carry ~1e-7 relative error;
 the deposit rounds each of a cell's n contributions to 2^-32 and sums them exactly in
-64-bit fixed point, then rounds the cell to FP32 once, so the summation adds at most
-n 2^-33 + 2^-24 of the cell's value (the bar below allows 1e-5, the bound an
+64-bit fixed point, then converts the cell to FP32 within one ulp, so the summation adds
+at most n 2^-33 + 2^-23 of the cell's value (the bar below allows 1e-5, the bound an
 arbitrary-order FP32 sum of n <= 10^4 terms would need, sqrt(n) 2^-24).  On
 top of that the mesh coordinate t = s/dx - 1/2 is an FP32 number, so each weight
 carries an absolute error of a few ulp(t) ~ |t| 2^-23: a cell reached by up to
