@@ -1083,14 +1083,23 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 // max |x| over count floats into *out (which the caller clears), as the bits of a
 // non-negative float, whose unsigned order is the numeric order with +inf above every
 // finite value and NaN above +inf: a non-finite entry gives a non-finite maximum.
+// One atomic per block: atomics on a single address serialise in L2, so the waves of a
+// block combine their maxima in LDS first.
+constexpr int kAbsmaxBlocks = 256;
 __global__ __launch_bounds__(kPartThreads) void k_absmax(const float* __restrict__ x, long count,
                                                          unsigned* __restrict__ out) {
+  __shared__ unsigned wave_max[kPartThreads / 64];
   unsigned m = 0;
   for (long i = (long)blockIdx.x * kPartThreads + threadIdx.x; i < count; i += (long)gridDim.x * kPartThreads)
     m = max(m, __float_as_uint(x[i]) & 0x7fffffffu);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
-  if (__lane_id() == 0) atomicMax(out, m);
+  if (__lane_id() == 0) wave_max[threadIdx.x / 64] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kPartThreads / 64; ++k) m = max(m, wave_max[k]);   // m: wave 0's maximum
+    atomicMax(out, m);
+  }
 }
 
 hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, float* rho, float mass,
@@ -1099,7 +1108,7 @@ hipError_t launch_deposit3(Lattice lat, Bins b, const float* s, BinBuffers bb, f
   // the scale of the fixed-point sums: max |weight| over the three components
   const hipError_t e = launch_fill(reinterpret_cast<float*>(wmax), 4, 0.0f, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_absmax, dim3(1024), dim3(kPartThreads), 0, st, weight, 3 * lat.npart, wmax);
+  hipLaunchKernelGGL(k_absmax, dim3(kAbsmaxBlocks), dim3(kPartThreads), 0, st, weight, 3 * lat.npart, wmax);
   COLA_TZ_DISPATCH(b.tz, hipLaunchKernelGGL((k_deposit_tiles<TZ, unsigned long long, 3>), dim3(tile_blocks(b)),
                                             dim3(TileDims<TZ>::TT), 0, st, lat, b, s, nullptr, bb.idx, bb.offset,
                                             bb.heavy, rho, mass, weight, wmax))
