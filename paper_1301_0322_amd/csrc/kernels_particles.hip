@@ -1084,14 +1084,20 @@ hipError_t launch_bin_scatter(Lattice lat, BinBuffers bb, hipStream_t st) {
 // non-negative float, whose unsigned order is the numeric order with +inf above every
 // finite value and NaN above +inf: a non-finite entry gives a non-finite maximum.
 // One atomic per block: atomics on a single address serialise in L2, so the waves of a
-// block combine their maxima in LDS first.
-constexpr int kAbsmaxBlocks = 256;
+// block combine their maxima in LDS first.  Each thread keeps four loads in flight.
+constexpr int kAbsmaxBlocks = 1024;
 __global__ __launch_bounds__(kPartThreads) void k_absmax(const float* __restrict__ x, long count,
                                                          unsigned* __restrict__ out) {
   __shared__ unsigned wave_max[kPartThreads / 64];
   unsigned m = 0;
-  for (long i = (long)blockIdx.x * kPartThreads + threadIdx.x; i < count; i += (long)gridDim.x * kPartThreads)
-    m = max(m, __float_as_uint(x[i]) & 0x7fffffffu);
+  const long step = (long)gridDim.x * kPartThreads;
+  long i = (long)blockIdx.x * kPartThreads + threadIdx.x;
+  for (; i + 3 * step < count; i += 4 * step) {
+    const unsigned a = __float_as_uint(x[i]), b = __float_as_uint(x[i + step]);
+    const unsigned c = __float_as_uint(x[i + 2 * step]), d = __float_as_uint(x[i + 3 * step]);
+    m = max(max(m, a & 0x7fffffffu), max(max(b & 0x7fffffffu, c & 0x7fffffffu), d & 0x7fffffffu));
+  }
+  for (; i < count; i += step) m = max(m, __float_as_uint(x[i]) & 0x7fffffffu);
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
   if (__lane_id() == 0) wave_max[threadIdx.x / 64] = m;
